@@ -1,0 +1,486 @@
+/*
+ * Radsort oracle: a plain, sequential CPU implementation of the LSD radix sort
+ * with O(sqrt n) extra space from "Parallel O(sqrt n) Overhead LSD Radix Sort"
+ * (Clausecker, Schintke).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this file.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code, header, table or
+ * helper with the GPU implementation.
+ *
+ * What it follows (paper sections, algorithms, equations):
+ *   - key(x, t): the n_t-tuple view of a key (Sec. 1).  Position t = n_t-1 is the
+ *     least significant digit and is sorted first (Alg. 2).
+ *   - blockat (Eq. 1), the state table and the data invariant (Sec. 2.1, 2.2).
+ *   - setup (Alg. 4), sizeOfNextBlock (Alg. 3), newBucketBlock and sortPhase
+ *     (Alg. 5), fixupPhase (Alg. 6), swap and finalize (Alg. 7).
+ *   - radixSortStep, the out-of-place round (Alg. 1).
+ *   - the space formula of Sec. 3 and the worked overhead numbers of Sec. 4.
+ *
+ * Readings taken where the printed text is ambiguous or garbled (each is also
+ * listed in the design notes of the repository):
+ *   G1  sizeOfNextBlock (Alg. 3) compares the LOGICAL index i with P's logical
+ *       index, not pi[i]: P stores logical indices (Sec. 2.1, Alg. 4, Alg. 6).
+ *   G2  finalize (Alg. 7): the physical home of logical block i_in is
+ *       i_in + sigma (logical sigma is the first A block, physical 2 sigma,
+ *       Eq. 1), not i_in - sigma.
+ *   G3  swap (Alg. 7) re-binds the (logical, physical) handle pairs so that each
+ *       pair keeps naming one block (Eq. 4); the loop counter i_in of finalize
+ *       is never changed by it, and the free slot becomes the block pulled from.
+ *   G4  setup: data lives at logical sigma .. sigma+floor(n/b)-1 and the tail
+ *       (n mod b elements, possibly zero) at logical f-1 = physical sigma.
+ *   G5  eager allocation: a bucket's next block is drawn as soon as its current
+ *       block becomes full (Alg. 5), so a bucket ends with a block that may be
+ *       empty; its partial length is in [0, b).
+ *   G7  integer keys: unsigned, ascending; digits by shift/mask for power-of-two
+ *       alphabets, by division for other alphabets; sigma is the same in every
+ *       round even when the top digit has fewer significant bits.
+ *
+ * Lemma 1 is asserted in its tight form: when a new output block is drawn during
+ * the scan, i_out < i_in, or i_out == i_in and the element just written was the
+ * last element of input block i_in (that block has then been read completely).
+ */
+#include "radsort_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+struct orc_state {
+    /* state table (Sec. 2.1) */
+    uint64_t n, sigma, nt, b, npi;
+    orc_elem *A;        /* the array being sorted, n elements */
+    orc_elem *T;        /* 2 sigma b scratch elements */
+    uint64_t f;         /* fill level */
+    uint64_t *pi;       /* logical -> physical block, n_pi entries */
+    uint64_t *Pi, *Pl;  /* partial blocks: logical index and length, sigma entries */
+    /* round temporaries (Sec. 2.3) */
+    orc_elem **Bnext, **Bend;
+    uint64_t *C, *S;
+    uint32_t *U;
+    uint64_t *pi2;
+    uint64_t i_out;
+    /* finalize temporaries (Sec. 2.4) */
+    uint64_t *pinv;
+    /* instrumentation */
+    uint64_t counters[ORC_NCOUNTERS];
+};
+
+/* ---- keys (Sec. 1; digit extraction by shift and mask, Sec. 4) ---------------- */
+
+static int is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+static uint64_t log2u(uint64_t x)
+{
+    uint64_t r = 0;
+    while ((1ull << r) < x) r++;
+    return r;
+}
+
+/* key(x, t): digit t of the n_t-digit base-sigma representation of x, where
+ * t = 0 is the most significant digit. */
+uint64_t orc_key(uint64_t x, uint64_t t, uint64_t sigma, uint64_t nt)
+{
+    uint64_t below = nt - 1 - t; /* number of less significant digits */
+    if (is_pow2(sigma)) {
+        uint64_t shift = below * log2u(sigma);
+        if (shift >= 64) return 0;
+        return (x >> shift) & (sigma - 1);
+    }
+    for (uint64_t k = 0; k < below; k++) x /= sigma;
+    return x % sigma;
+}
+
+/* ---- blocks (Eq. 1) ------------------------------------------------------------- */
+
+static orc_elem *blockat(orc_state *st, uint64_t i)
+{
+    if (i < 2 * st->sigma) return st->T + i * st->b;
+    return st->A + (i - 2 * st->sigma) * st->b;
+}
+
+/* ---- life cycle ----------------------------------------------------------------- */
+
+orc_state *orc_create(uint64_t n, uint64_t sigma, uint64_t nt, uint64_t b)
+{
+    if (sigma < 2 || nt < 1 || b < 1) return NULL;
+    orc_state *st = calloc(1, sizeof *st);
+    if (!st) return NULL;
+    st->n = n;
+    st->sigma = sigma;
+    st->nt = nt;
+    st->b = b;
+    st->npi = n / b + 2 * sigma; /* state table, Sec. 2.1 */
+    st->A = calloc(n ? n : 1, sizeof(orc_elem));
+    st->T = calloc(2 * sigma * b, sizeof(orc_elem));
+    st->pi = calloc(st->npi, sizeof(uint64_t));
+    st->pi2 = calloc(st->npi, sizeof(uint64_t));
+    st->pinv = calloc(st->npi, sizeof(uint64_t));
+    st->U = calloc(st->npi, sizeof(uint32_t));
+    st->Pi = calloc(sigma, sizeof(uint64_t));
+    st->Pl = calloc(sigma, sizeof(uint64_t));
+    st->C = calloc(sigma, sizeof(uint64_t));
+    st->S = calloc(sigma, sizeof(uint64_t));
+    st->Bnext = calloc(sigma, sizeof(orc_elem *));
+    st->Bend = calloc(sigma, sizeof(orc_elem *));
+    if (!st->A || !st->T || !st->pi || !st->pi2 || !st->pinv || !st->U || !st->Pi ||
+        !st->Pl || !st->C || !st->S || !st->Bnext || !st->Bend) {
+        orc_destroy(st);
+        return NULL;
+    }
+    return st;
+}
+
+void orc_destroy(orc_state *st)
+{
+    if (!st) return;
+    free(st->A); free(st->T); free(st->pi); free(st->pi2); free(st->pinv);
+    free(st->U); free(st->Pi); free(st->Pl); free(st->C); free(st->S);
+    free(st->Bnext); free(st->Bend);
+    free(st);
+}
+
+void orc_load(orc_state *st, const uint64_t *keys, const uint64_t *vals)
+{
+    for (uint64_t i = 0; i < st->n; i++) {
+        st->A[i].key = keys[i];
+        st->A[i].val = vals ? vals[i] : 0;
+    }
+}
+
+void orc_store(const orc_state *st, uint64_t *keys, uint64_t *vals)
+{
+    for (uint64_t i = 0; i < st->n; i++) {
+        keys[i] = st->A[i].key;
+        if (vals) vals[i] = st->A[i].val;
+    }
+}
+
+/* ---- setup (Alg. 4) --------------------------------------------------------------- */
+
+void orc_setup(orc_state *st)
+{
+    uint64_t sigma = st->sigma, b = st->b, n = st->n;
+    st->f = sigma + n / b + 1;
+    for (uint64_t i = 0; i < sigma; i++) st->pi[i] = i;                 /* head start */
+    for (uint64_t i = sigma; i + 1 < st->f; i++) st->pi[i] = i + sigma;  /* blocks of A */
+    for (uint64_t i = st->f - 1; i < st->npi; i++)                       /* the rest, in T */
+        st->pi[i] = sigma + (i - (st->f - 1));
+    memset(st->T, 0, 2 * sigma * b * sizeof(orc_elem));                  /* dummy fill */
+    memcpy(blockat(st, sigma), st->A + b * (n / b), (n % b) * sizeof(orc_elem));
+    st->Pi[0] = st->f - 1;                                               /* the tail */
+    st->Pl[0] = n % b;
+    for (uint64_t i = 1; i < sigma; i++) {                               /* dummies */
+        st->Pi[i] = st->npi;
+        st->Pl[i] = 0;
+    }
+}
+
+/* ---- sizeOfNextBlock (Alg. 3, reading G1) ---------------------------------------- */
+
+static uint64_t size_of_next_block(const orc_state *st, uint64_t i, uint64_t *iP)
+{
+    if (*iP < st->sigma && st->Pi[*iP] == i) {
+        uint64_t l = st->Pl[*iP];
+        (*iP)++;
+        return l;
+    }
+    return st->b;
+}
+
+/* ---- newBucketBlock and sortPhase (Alg. 5) -------------------------------------- */
+
+static void new_bucket_block(orc_state *st, uint64_t c)
+{
+    if (st->i_out >= st->npi) { st->counters[ORC_C_POOL_OVERRUN]++; return; }
+    orc_elem *p = blockat(st, st->pi[st->i_out]);
+    st->Bnext[c] = p;
+    st->Bend[c] = p + st->b;
+    st->C[c]++;
+    st->U[st->i_out] = (uint32_t)c;
+    st->i_out++;
+}
+
+void orc_sort_phase(orc_state *st, uint64_t t)
+{
+    uint64_t sigma = st->sigma, iP = 0;
+    for (uint64_t c = 0; c < sigma; c++) st->C[c] = 0;
+    st->i_out = 0;
+    for (uint64_t c = 0; c < sigma; c++) new_bucket_block(st, c);
+    for (uint64_t i_in = sigma; i_in < st->f; i_in++) {
+        orc_elem *p_in = blockat(st, st->pi[i_in]);
+        uint64_t l = size_of_next_block(st, i_in, &iP);
+        for (uint64_t j = 0; j < l; j++) {
+            uint64_t c = orc_key(p_in[j].key, t, sigma, st->nt);
+            orc_elem *p_next = st->Bnext[c];
+            *p_next = p_in[j];
+            if (p_next + 1 == st->Bend[c]) {
+                /* Lemma 1, tight form */
+                if (st->i_out < i_in) {
+                    /* strict case of the lemma */
+                } else if (st->i_out == i_in && j + 1 == l) {
+                    st->counters[ORC_C_LEMMA1_EQUAL]++;
+                } else {
+                    st->counters[ORC_C_LEMMA1_VIOLATION]++;
+                }
+                new_bucket_block(st, c);
+            } else {
+                st->Bnext[c] = p_next + 1;
+            }
+        }
+    }
+}
+
+/* ---- fixupPhase (Alg. 6) ------------------------------------------------------------ */
+
+void orc_fixup_phase(orc_state *st)
+{
+    uint64_t sigma = st->sigma, npi = st->npi, i_out = st->i_out;
+    if (npi - i_out < sigma) {            /* Lemma 2 */
+        st->counters[ORC_C_LEMMA2_VIOLATION]++;
+        return;
+    }
+    st->S[0] = sigma;
+    for (uint64_t i = 1; i < sigma; i++) st->S[i] = st->S[i - 1] + st->C[i - 1];
+    for (uint64_t i = 0; i < sigma; i++) st->pi2[i] = st->pi[i_out + i];   /* head start */
+    for (uint64_t i = 0; i < i_out; i++) {
+        uint64_t c = st->U[i];
+        st->pi2[st->S[c]] = st->pi[i];
+        orc_elem *base = blockat(st, st->pi[i]);
+        if (st->Bend[c] == base + st->b) {                                  /* partial? */
+            st->Pi[c] = st->S[c];
+            st->Pl[c] = (uint64_t)(st->Bnext[c] - base);
+        }
+        st->S[c]++;
+    }
+    for (uint64_t i = i_out + sigma; i < npi; i++) st->pi2[i] = st->pi[i]; /* the rest */
+    st->f = i_out + sigma;
+    uint64_t *tmp = st->pi;
+    st->pi = st->pi2;
+    st->pi2 = tmp;
+}
+
+void orc_round(orc_state *st, uint64_t t)
+{
+    orc_sort_phase(st, t);
+    orc_fixup_phase(st);
+    st->counters[ORC_C_ROUNDS]++;
+}
+
+/* ---- swap and finalize (Alg. 7, readings G2 and G3) ------------------------------ */
+
+/* Re-bind logical index i to physical block j in both pi and its inverse. */
+static void bind(orc_state *st, uint64_t i, uint64_t j)
+{
+    st->pi[i] = j;
+    st->pinv[j] = i;
+}
+
+void orc_finalize(orc_state *st)
+{
+    uint64_t sigma = st->sigma, b = st->b, nb = st->n / st->b, k = 0, iP = 0;
+    uint64_t i_free = 0, j_free = st->pi[0];
+    for (uint64_t i = 0; i < st->npi; i++) st->pinv[st->pi[i]] = i;
+    for (uint64_t i_in = sigma; i_in < sigma + nb; i_in++) {
+        uint64_t j_in = st->pi[i_in];
+        uint64_t j_out = i_in + sigma;              /* G2: home of logical i_in */
+        uint64_t i_out = st->pinv[j_out];
+        if (sigma <= i_out && i_out < i_in) st->counters[ORC_C_FINALIZE_HOME_TAKEN]++;
+        if (i_in < i_out && i_out < st->f) {
+            /* another allocated block still to be pulled sits at the home: push it */
+            memcpy(blockat(st, j_free), blockat(st, j_out), b * sizeof(orc_elem));
+            st->counters[ORC_C_FINALIZE_COPIES]++;
+            bind(st, i_out, j_free);                /* swap(i_out, j_out, i_free, j_free) */
+            bind(st, i_free, j_out);
+            i_out = i_free;                         /* G3: the pair (i_out, j_out) */
+        }
+        uint64_t l = size_of_next_block(st, i_in, &iP);
+        memmove(st->A + k, blockat(st, j_in), l * sizeof(orc_elem));   /* pull */
+        st->counters[ORC_C_FINALIZE_COPIES]++;
+        k += l;
+        bind(st, i_in, j_out);                      /* swap(i_out, j_out, i_in, j_in) */
+        bind(st, i_out, j_in);
+        if (j_in != j_out) {                        /* G3: the block pulled from is free */
+            i_free = i_out;
+            j_free = j_in;
+        }
+    }
+    for (uint64_t i_in = sigma + nb; i_in < st->f; i_in++) {
+        uint64_t j_in = st->pi[i_in];
+        if (j_in >= 2 * sigma) st->counters[ORC_C_FINALIZE_TAIL_NOT_IN_T]++;
+        uint64_t l = size_of_next_block(st, i_in, &iP);
+        memmove(st->A + k, blockat(st, j_in), l * sizeof(orc_elem));
+        st->counters[ORC_C_FINALIZE_COPIES]++;
+        k += l;
+    }
+    if (k != st->n) st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
+}
+
+/* ---- the driver (Alg. 2) ----------------------------------------------------------- */
+
+int orc_radsort(uint64_t *keys, uint64_t *vals, uint64_t n, uint64_t sigma, uint64_t nt,
+                uint64_t b)
+{
+    orc_state *st = orc_create(n, sigma, nt, b);
+    if (!st) return -1;
+    orc_load(st, keys, vals);
+    orc_setup(st);
+    for (uint64_t t = nt; t-- > 0;) orc_round(st, t);
+    orc_finalize(st);
+    orc_store(st, keys, vals);
+    int bad = 0;
+    for (int c = ORC_C_FIRST_ERROR; c < ORC_NCOUNTERS; c++) bad |= st->counters[c] != 0;
+    orc_destroy(st);
+    return bad ? -2 : 0;
+}
+
+/* ---- inspection --------------------------------------------------------------------- */
+
+uint64_t orc_npi(const orc_state *st) { return st->npi; }
+uint64_t orc_f(const orc_state *st) { return st->f; }
+uint64_t orc_i_out(const orc_state *st) { return st->i_out; }
+
+void orc_get_pi(const orc_state *st, uint64_t *out)
+{
+    memcpy(out, st->pi, st->npi * sizeof(uint64_t));
+}
+
+void orc_get_P(const orc_state *st, uint64_t *idx, uint64_t *len)
+{
+    memcpy(idx, st->Pi, st->sigma * sizeof(uint64_t));
+    memcpy(len, st->Pl, st->sigma * sizeof(uint64_t));
+}
+
+void orc_get_C(const orc_state *st, uint64_t *out)
+{
+    memcpy(out, st->C, st->sigma * sizeof(uint64_t));
+}
+
+void orc_get_counters(const orc_state *st, uint64_t *out)
+{
+    memcpy(out, st->counters, sizeof st->counters);
+}
+
+/* The used elements of the allocated blocks sigma .. f-1 in logical order
+ * (data invariant, clause 5), found by walking P as sizeOfNextBlock does. */
+uint64_t orc_get_logical(orc_state *st, uint64_t *keys, uint64_t *vals)
+{
+    uint64_t k = 0, iP = 0;
+    for (uint64_t i = st->sigma; i < st->f; i++) {
+        orc_elem *p = blockat(st, st->pi[i]);
+        uint64_t l = size_of_next_block(st, i, &iP);
+        for (uint64_t j = 0; j < l; j++, k++) {
+            if (k < st->n) {
+                keys[k] = p[j].key;
+                if (vals) vals[k] = p[j].val;
+            }
+        }
+    }
+    return k;
+}
+
+/* The data invariant of Sec. 2.2, clauses 1-4 (clause 5 is checked by the tests
+ * from the logical sequence).  Returns 0 when it holds, else the clause number. */
+int orc_check_invariant(orc_state *st)
+{
+    uint64_t npi = st->npi, sigma = st->sigma;
+    unsigned char *seen = calloc(npi, 1);
+    if (!seen) return -1;
+    int bad = 0;
+    for (uint64_t i = 0; i < npi && !bad; i++) {
+        if (st->pi[i] >= npi || seen[st->pi[i]]) bad = 1;
+        else seen[st->pi[i]] = 1;
+    }
+    free(seen);
+    if (bad) return 1;
+    /* clause 2: real entries of P ascending and inside the allocated range */
+    uint64_t prev = 0;
+    int have_prev = 0;
+    for (uint64_t i = 0; i < sigma; i++) {
+        if (st->Pi[i] == npi) continue; /* dummy entry of setup */
+        if (st->Pi[i] < sigma || st->Pi[i] >= st->f || st->Pl[i] >= st->b) return 2;
+        if (have_prev && st->Pi[i] <= prev) return 2;
+        prev = st->Pi[i];
+        have_prev = 1;
+    }
+    /* clause 3: f-1 is a partial block */
+    int found = 0;
+    for (uint64_t i = 0; i < sigma; i++) found |= st->Pi[i] == st->f - 1;
+    if (!found) return 3;
+    /* clause 4: the allocated range fits between the head start and n_pi */
+    if (st->f <= sigma || st->f > npi) return 4;
+    /* the used elements add up to n */
+    uint64_t k = 0, iP = 0;
+    for (uint64_t i = sigma; i < st->f; i++) k += size_of_next_block(st, i, &iP);
+    if (k != st->n) return 5;
+    return 0;
+}
+
+/* ---- out-of-place LSD (Alg. 1) ------------------------------------------------------- */
+
+static void radix_sort_step(orc_elem *Aout, const orc_elem *A, uint64_t n, uint64_t t,
+                            uint64_t sigma, uint64_t nt, uint64_t *H)
+{
+    for (uint64_t c = 0; c < sigma; c++) H[c] = 0;
+    for (uint64_t i = 0; i < n; i++) H[orc_key(A[i].key, t, sigma, nt)]++;
+    uint64_t s = 0;                                   /* S: prefix sum over H */
+    for (uint64_t c = 0; c < sigma; c++) {
+        uint64_t h = H[c];
+        H[c] = s;
+        s += h;
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t c = orc_key(A[i].key, t, sigma, nt);
+        Aout[H[c]] = A[i];
+        H[c]++;
+    }
+}
+
+/* Runs `rounds` out-of-place rounds, t = n_t-1, n_t-2, ... (all n_t when rounds
+ * equals n_t).  Returns 0, or -1 when memory runs out. */
+int orc_oop_lsd(uint64_t *keys, uint64_t *vals, uint64_t n, uint64_t sigma, uint64_t nt,
+                uint64_t rounds)
+{
+    orc_elem *a = malloc((n ? n : 1) * sizeof(orc_elem));
+    orc_elem *a2 = malloc((n ? n : 1) * sizeof(orc_elem));
+    uint64_t *H = malloc(sigma * sizeof(uint64_t));
+    if (!a || !a2 || !H) { free(a); free(a2); free(H); return -1; }
+    for (uint64_t i = 0; i < n; i++) {
+        a[i].key = keys[i];
+        a[i].val = vals ? vals[i] : 0;
+    }
+    for (uint64_t r = 0; r < rounds && r < nt; r++) {
+        radix_sort_step(a2, a, n, nt - 1 - r, sigma, nt, H);
+        orc_elem *tmp = a; a = a2; a2 = tmp;
+    }
+    for (uint64_t i = 0; i < n; i++) {
+        keys[i] = a[i].key;
+        if (vals) vals[i] = a[i].val;
+    }
+    free(a); free(a2); free(H);
+    return 0;
+}
+
+/* Histograms of every key position: out[t * sigma + c] = #{i : key(x_i, t) = c}. */
+void orc_histograms(const uint64_t *keys, uint64_t n, uint64_t sigma, uint64_t nt,
+                    uint64_t *out)
+{
+    memset(out, 0, nt * sigma * sizeof(uint64_t));
+    for (uint64_t i = 0; i < n; i++)
+        for (uint64_t t = 0; t < nt; t++) out[t * sigma + orc_key(keys[i], t, sigma, nt)]++;
+}
+
+/* ---- extra space (Sec. 3 "Space"; worked numbers in Sec. 4) ------------------------ */
+
+/* Bytes of storage besides A: T, then B, C, S, P, then pi, pi', U per block, with
+ * pi^{-1} reusing pi'.  elem_bytes is the element size, ptr_bytes the size of a
+ * pointer in B and int_bytes the size of the integers in C, S, P, pi, pi'. */
+uint64_t orc_extra_bytes(uint64_t n, uint64_t sigma, uint64_t b, uint64_t elem_bytes,
+                         uint64_t ptr_bytes, uint64_t int_bytes)
+{
+    uint64_t npi = n / b + 2 * sigma;
+    uint64_t u_bytes = sigma <= 256 ? 1 : (sigma <= 65536 ? 2 : 4);
+    uint64_t t_bytes = 2 * sigma * b * elem_bytes;
+    uint64_t bucket_bytes = sigma * (2 * ptr_bytes + int_bytes + int_bytes + 2 * int_bytes);
+    uint64_t block_bytes = npi * (2 * int_bytes + u_bytes);
+    return t_bytes + bucket_bytes + block_bytes;
+}
