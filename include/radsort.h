@@ -1,0 +1,165 @@
+/*
+ * radsort.h -- C ABI of the MI355X (gfx950) Radsort library.
+ *
+ * Radsort is the stable LSD radix sort with O(sqrt n) extra space of
+ * "Parallel O(sqrt n) Overhead LSD Radix Sort" (Clausecker, Schintke).  The
+ * problem statement (Sec. 1) is: sort an array A of n elements whose keys are
+ * n_t-tuples of digits over an alphabet of sigma symbols into lexicographic
+ * order by stable rounds on key positions n_t-1, ..., 0.  Here keys are unsigned
+ * integers of key_bytes bytes split into digits of digit_bits bits, so sigma =
+ * 2^digit_bits and n_t = ceil(8 key_bytes / digit_bits); position n_t-1 is the
+ * least significant digit.  The result is ascending by unsigned key and stable.
+ *
+ * Conventions for every call:
+ *   - keys and payload are DEVICE pointers to n contiguous elements each
+ *     (structure of arrays; the two ranges must not overlap).  They stay owned by
+ *     the caller.  Their contents are undefined from the call until the stream
+ *     reaches the end of the work the call enqueued.
+ *   - stream is a hipStream_t (NULL = the null stream).  Work is enqueued on it;
+ *     unless stated otherwise a call returns without waiting for the GPU.
+ *   - workspace: device memory of at least the queried size, owned by the caller,
+ *     untouched by anyone else until the enqueued work has finished.  When
+ *     opts->workspace is NULL the library allocates the workspace itself for the
+ *     call and waits for the stream before freeing it.
+ *   - return value: RADSORT_OK (0) or a negative RADSORT_E_* code.  Argument
+ *     errors are detected before anything is enqueued and leave the data as it
+ *     was.  After a device error the data is undefined.
+ */
+#ifndef RADSORT_H
+#define RADSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RADSORT_OK 0
+#define RADSORT_E_INVALID (-1)      /* bad argument: null pointer with n > 0, widths, b */
+#define RADSORT_E_NOMEM (-2)        /* allocation failed or workspace too small */
+#define RADSORT_E_DEVICE (-3)       /* a HIP call failed; see radsort_strerror */
+#define RADSORT_E_UNSUPPORTED (-4)  /* n >= 2^32 or digit_bits > 11 */
+#define RADSORT_E_TIMEOUT (-5)      /* a device-side bounded wait gave up */
+
+/* flags of radsort_opts */
+#define RADSORT_F_CHECK 1u          /* wait for the stream and report device-side errors */
+
+typedef struct radsort_opts {
+    uint32_t block_elems;     /* b: block size in elements, a power of two in [64, 65536];
+                                 0 selects 1024 */
+    uint32_t tile_elems;      /* reserved, 0 */
+    void* workspace;          /* device workspace, or NULL: allocated per call */
+    uint64_t workspace_bytes; /* its size in bytes */
+    uint32_t flags;           /* RADSORT_F_* */
+} radsort_opts;
+
+typedef struct radsort_stats {
+    uint64_t workspace_bytes;   /* extra device bytes of the last sort (peak extra memory) */
+    uint64_t input_bytes;       /* n * (key_bytes + payload_bytes) of the last sort */
+    uint32_t rounds;            /* digit rounds run */
+    uint32_t error_bits;        /* device error word of the last checked call */
+} radsort_stats;
+
+/*
+ * radsort_sort_pairs -- sort keys[0..n) in place, ascending and stable, moving
+ * payload[i] with keys[i].  Radsort, the driver of Alg. 2: setup (Alg. 4), then
+ * for t = n_t-1 .. 0 a sort phase (Alg. 5) and a fixup phase (Alg. 6), then
+ * finalize (Alg. 7).  The digit histograms of all key positions are taken up
+ * front in one pass (the histogram loop of Alg. 1, run for all positions as the
+ * evaluated "generic" variant of Sec. 5 does).
+ *   key_bytes      4 or 8 (uint32 / uint64 keys; signed or float keys are not
+ *                  handled: the order is that of the unsigned bit patterns)
+ *   payload_bytes  0 (payload must be NULL), 4 or 8
+ *   digit_bits     1 .. 11
+ *   opts           may be NULL (b = 1024, library-allocated workspace)
+ * Extra device memory is the workspace only: radsort_workspace_bytes().
+ * n <= 1 returns RADSORT_OK without touching the data.
+ */
+int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
+                       int payload_bytes, int digit_bits, const radsort_opts* opts,
+                       void* stream);
+
+/* radsort_sort -- radsort_sort_pairs without payload and with default options. */
+int radsort_sort(void* keys, uint64_t n, int key_bytes, int digit_bits, void* stream);
+
+/* Workspace bytes radsort_sort_pairs needs for these arguments: the scratch
+ * blocks T (2 sigma b elements, Sec. 2.1), two n_pi-entry block permutations,
+ * the histograms and per-round closed forms, the look-back status ring and the
+ * finalize scratch (which reuses the ring's memory).  0 on invalid arguments. */
+uint64_t radsort_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes,
+                                 int digit_bits, const radsort_opts* opts);
+
+/*
+ * radsort_oop_sort_pairs -- the out-of-place LSD radix sort of Alg. 1 on the
+ * same tile code: n_t rounds, each a stable counting sort from one array into a
+ * second one of n elements, ping-ponging between the caller's arrays and
+ * workspace buffers.  Same arguments, result and ownership as
+ * radsort_sort_pairs; it needs n (key_bytes + payload_bytes) extra bytes plus the
+ * histogram and look-back state: radsort_oop_workspace_bytes().
+ */
+int radsort_oop_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
+                           int payload_bytes, int digit_bits, const radsort_opts* opts,
+                           void* stream);
+uint64_t radsort_oop_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes,
+                                     int digit_bits, const radsort_opts* opts);
+
+/*
+ * radsort_histograms -- the up-front digit histograms alone: counts[t * sigma + c]
+ * = number of i with key(keys[i], t) = c, t = 0 the most significant position
+ * (the first loop of Alg. 1 for every position).  counts is a device array of
+ * n_t * sigma uint32 that the call overwrites.
+ */
+int radsort_histograms(const void* keys, uint64_t n, int key_bytes, int digit_bits,
+                       uint32_t* counts, void* stream);
+
+/* Statistics of the last completed sort call of this process. */
+int radsort_last_stats(radsort_stats* out);
+
+/* Text for a return code (and, after RADSORT_E_DEVICE, the HIP error). */
+const char* radsort_strerror(int code);
+
+/* ---------------------------------------------------------------------------
+ * Step interface: the Radsort state (A, T, pi, P, f of Sec. 2.1) kept between
+ * calls.  It runs the phases one at a time, exposes the permuted representation
+ * between rounds (Sec. 4.1: the data can be read in logical order without
+ * finalizing), and lets tests compare every round with the sequential algorithm.
+ * ------------------------------------------------------------------------- */
+typedef struct radsort_state radsort_state;
+
+/* Creates a state over caller-owned keys/payload (device, n elements each; they
+ * must outlive the state).  Allocates the workspace unless opts->workspace is
+ * given.  Nothing is enqueued. */
+int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_t n,
+                         int key_bytes, int payload_bytes, int digit_bits,
+                         const radsort_opts* opts);
+/* Enqueues the digit histograms, the closed-form plan and setup (Alg. 4). */
+int radsort_state_setup(radsort_state* st, void* stream);
+/* Enqueues the next round (sort phase, Alg. 5, and fixup phase, Alg. 6).  Rounds
+ * run t = n_t-1 first; at most n_t rounds per setup. */
+int radsort_state_round(radsort_state* st, void* stream);
+/* Enqueues finalize (Alg. 7): the data ends sorted in keys/payload. */
+int radsort_state_finalize(radsort_state* st, void* stream);
+/* Finalize by the one-workgroup sequential form of Alg. 7 (slow; a test aid). */
+int radsort_state_finalize_sequential(radsort_state* st, void* stream);
+/* Waits for the stream and copies the state to host memory: pi (n_pi uint32),
+ * P (sigma logical indices and sigma lengths, uint32) and f.  Any of the output
+ * pointers may be NULL.  Returns RADSORT_E_TIMEOUT if a device wait gave up. */
+int radsort_state_read(radsort_state* st, uint32_t* pi, uint32_t* P_idx, uint32_t* P_len,
+                       uint32_t* f, void* stream);
+/* Enqueues a gather of the used elements of logical blocks sigma .. f-1 in
+ * logical order (data invariant, clause 5) into device arrays keys_out /
+ * payload_out of n elements each. */
+int radsort_state_logical(radsort_state* st, void* keys_out, void* payload_out,
+                          void* stream);
+/* n_pi, sigma and n_t of the state. */
+int radsort_state_dims(const radsort_state* st, uint32_t* npi, uint32_t* sigma,
+                       uint32_t* nt);
+/* Frees the state and the workspace it allocated (call after the stream is done). */
+int radsort_state_destroy(radsort_state* st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADSORT_H */

@@ -1,0 +1,287 @@
+"""Radsort on MI355X: thin ctypes binding of libradsort.so (include/radsort.h).
+
+Every step of the sort runs in the library's HIP kernels.  This module only
+marshals arguments: device pointers and sizes from torch tensors, the current
+HIP stream, and return codes into exceptions.  There is no CPU fallback: when the
+library is missing, every call raises.
+
+    import paper_2607_05302_amd as radsort
+    radsort.sort_(keys, payload)            # in place, ascending, stable
+
+Keys are read as unsigned integers of their width: torch.uint32 / torch.int32
+(4 bytes) or torch.uint64 / torch.int64 (8 bytes), bit patterns taken as
+unsigned.  The payload, optional, is any 4- or 8-byte integer tensor of the same
+length.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libradsort.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_TIMEOUT = 0, -1, -2, -3, -4, -5
+F_CHECK = 1
+
+# every function declared in include/radsort.h
+ABI = [
+    "radsort_sort_pairs", "radsort_sort", "radsort_workspace_bytes", "radsort_oop_sort_pairs",
+    "radsort_oop_workspace_bytes", "radsort_histograms", "radsort_last_stats",
+    "radsort_strerror", "radsort_state_create", "radsort_state_setup", "radsort_state_round",
+    "radsort_state_finalize", "radsort_state_finalize_sequential", "radsort_state_read",
+    "radsort_state_logical", "radsort_state_dims", "radsort_state_destroy",
+]
+
+
+class RadsortError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"radsort error {code}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("block_elems", ctypes.c_uint32), ("tile_elems", ctypes.c_uint32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_uint64), ("input_bytes", ctypes.c_uint64),
+                ("rounds", ctypes.c_uint32), ("error_bits", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libradsort.so; raises if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libradsort.so not found at {p}: run __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    vp, u64, i32, u32p = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_uint32)
+    op = ctypes.POINTER(Opts)
+    sig = {
+        "radsort_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
+        "radsort_sort": (i32, [vp, u64, i32, i32, vp]),
+        "radsort_workspace_bytes": (u64, [u64, i32, i32, i32, op]),
+        "radsort_oop_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
+        "radsort_oop_workspace_bytes": (u64, [u64, i32, i32, i32, op]),
+        "radsort_histograms": (i32, [vp, u64, i32, i32, vp, vp]),
+        "radsort_last_stats": (i32, [ctypes.POINTER(Stats)]),
+        "radsort_strerror": (ctypes.c_char_p, [i32]),
+        "radsort_state_create": (i32, [ctypes.POINTER(vp), vp, vp, u64, i32, i32, i32, op]),
+        "radsort_state_setup": (i32, [vp, vp]),
+        "radsort_state_round": (i32, [vp, vp]),
+        "radsort_state_finalize": (i32, [vp, vp]),
+        "radsort_state_finalize_sequential": (i32, [vp, vp]),
+        "radsort_state_read": (i32, [vp, u32p, u32p, u32p, u32p, vp]),
+        "radsort_state_logical": (i32, [vp, vp, vp, vp]),
+        "radsort_state_dims": (i32, [vp, u32p, u32p, u32p]),
+        "radsort_state_destroy": (i32, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().radsort_strerror(code).decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise RadsortError(rc, strerror(rc))
+
+
+def _width(t) -> int:
+    import torch
+    w = {torch.int32: 4, torch.uint32: 4, torch.int64: 8, torch.uint64: 8}.get(t.dtype)
+    if w is None:
+        raise TypeError(f"unsupported dtype {t.dtype}: need a 4- or 8-byte integer tensor")
+    return w
+
+
+def _stream(stream, device):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _opts(block_elems=1024, workspace=None, flags=0):
+    o = Opts()
+    o.block_elems = block_elems
+    o.tile_elems = 0
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    o.flags = flags
+    return o
+
+
+def _validate(keys, payload):
+    if not keys.is_cuda:
+        raise ValueError("keys must be a device tensor")
+    if not keys.is_contiguous():
+        raise ValueError("keys must be contiguous")
+    if payload is not None:
+        if payload.device != keys.device or not payload.is_contiguous():
+            raise ValueError("payload must be a contiguous tensor on the keys' device")
+        if payload.numel() != keys.numel():
+            raise ValueError("payload and keys differ in length")
+    return _width(keys), (_width(payload) if payload is not None else 0)
+
+
+def workspace_bytes(n, key_bytes=4, payload_bytes=0, digit_bits=8, block_elems=1024) -> int:
+    o = _opts(block_elems)
+    return int(load().radsort_workspace_bytes(n, key_bytes, payload_bytes, digit_bits,
+                                              ctypes.byref(o)))
+
+
+def oop_workspace_bytes(n, key_bytes=4, payload_bytes=0, digit_bits=8, block_elems=1024) -> int:
+    o = _opts(block_elems)
+    return int(load().radsort_oop_workspace_bytes(n, key_bytes, payload_bytes, digit_bits,
+                                                  ctypes.byref(o)))
+
+
+def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, workspace=None,
+          check=False):
+    """Radsort in place on the current stream (radsort_sort_pairs)."""
+    kb, vb = _validate(keys, payload)
+    o = _opts(block_elems, workspace, F_CHECK if check else 0)
+    with _device(keys):
+        rc = load().radsort_sort_pairs(
+            ctypes.c_void_p(keys.data_ptr()),
+            ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
+            keys.numel(), kb, vb, digit_bits, ctypes.byref(o), _stream(stream, keys.device))
+    _check(rc)
+    return keys, payload
+
+
+def oop_sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, workspace=None,
+              check=False):
+    """The out-of-place LSD baseline of Alg. 1, in place from the caller's view."""
+    kb, vb = _validate(keys, payload)
+    o = _opts(block_elems, workspace, F_CHECK if check else 0)
+    with _device(keys):
+        rc = load().radsort_oop_sort_pairs(
+            ctypes.c_void_p(keys.data_ptr()),
+            ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
+            keys.numel(), kb, vb, digit_bits, ctypes.byref(o), _stream(stream, keys.device))
+    _check(rc)
+    return keys, payload
+
+
+def histograms(keys, digit_bits=8, stream=None):
+    """Digit histograms of every key position: int32 tensor [n_t, sigma] (as uint32 bits)."""
+    import torch
+    kb, _ = _validate(keys, None)
+    sigma = 1 << digit_bits
+    nt = (8 * kb + digit_bits - 1) // digit_bits
+    out = torch.empty(nt * sigma, dtype=torch.int32, device=keys.device)
+    with _device(keys):
+        rc = load().radsort_histograms(ctypes.c_void_p(keys.data_ptr()), keys.numel(), kb,
+                                       digit_bits, ctypes.c_void_p(out.data_ptr()),
+                                       _stream(stream, keys.device))
+    _check(rc)
+    return out.view(nt, sigma)
+
+
+def last_stats() -> dict:
+    s = Stats()
+    _check(load().radsort_last_stats(ctypes.byref(s)))
+    return {"workspace_bytes": s.workspace_bytes, "input_bytes": s.input_bytes,
+            "rounds": s.rounds, "error_bits": s.error_bits}
+
+
+class _device:
+    """Makes the tensor's device current for the duration of a call."""
+
+    def __init__(self, t):
+        self.t = t
+
+    def __enter__(self):
+        import torch
+        self.ctx = torch.cuda.device(self.t.device)
+        self.ctx.__enter__()
+
+    def __exit__(self, *exc):
+        self.ctx.__exit__(*exc)
+
+
+class State:
+    """The step interface: setup, rounds, finalize, and inspection between them."""
+
+    def __init__(self, keys, payload=None, digit_bits=8, block_elems=1024, workspace=None):
+        kb, vb = _validate(keys, payload)
+        self.keys, self.payload = keys, payload
+        self.kb, self.vb, self.digit_bits = kb, vb, digit_bits
+        o = _opts(block_elems, workspace)
+        h = ctypes.c_void_p()
+        with _device(keys):
+            rc = load().radsort_state_create(
+                ctypes.byref(h), ctypes.c_void_p(keys.data_ptr()),
+                ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
+                keys.numel(), kb, vb, digit_bits, ctypes.byref(o))
+        _check(rc)
+        self._h = h
+        npi, sigma, nt = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(load().radsort_state_dims(h, ctypes.byref(npi), ctypes.byref(sigma),
+                                         ctypes.byref(nt)))
+        self.npi, self.sigma, self.nt = npi.value, sigma.value, nt.value
+
+    def _call(self, name, *args, stream=None):
+        with _device(self.keys):
+            rc = getattr(load(), name)(self._h, *args, _stream(stream, self.keys.device))
+        _check(rc)
+
+    def setup(self, stream=None):
+        self._call("radsort_state_setup", stream=stream)
+
+    def round(self, stream=None):
+        self._call("radsort_state_round", stream=stream)
+
+    def finalize(self, stream=None):
+        self._call("radsort_state_finalize", stream=stream)
+
+    def finalize_sequential(self, stream=None):
+        self._call("radsort_state_finalize_sequential", stream=stream)
+
+    def read(self, stream=None):
+        """(pi, P_idx, P_len, f) as numpy arrays; waits for the stream."""
+        import numpy as np
+        pi = np.zeros(self.npi, np.uint32)
+        pidx = np.zeros(self.sigma, np.uint32)
+        plen = np.zeros(self.sigma, np.uint32)
+        f = np.zeros(1, np.uint32)
+        P = ctypes.POINTER(ctypes.c_uint32)
+        self._call("radsort_state_read", pi.ctypes.data_as(P), pidx.ctypes.data_as(P),
+                   plen.ctypes.data_as(P), f.ctypes.data_as(P), stream=stream)
+        return pi, pidx, plen, int(f[0])
+
+    def logical(self, stream=None):
+        """The permuted representation gathered in logical order (new tensors)."""
+        import torch
+        ok = torch.empty_like(self.keys)
+        ov = torch.empty_like(self.payload) if self.payload is not None else None
+        self._call("radsort_state_logical", ctypes.c_void_p(ok.data_ptr()),
+                   ctypes.c_void_p(ov.data_ptr() if ov is not None else None), stream=stream)
+        return ok, ov
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().radsort_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

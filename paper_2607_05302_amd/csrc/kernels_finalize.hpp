@@ -1,0 +1,555 @@
+// Parallel finalize (Alg. 7 in the parallel form sketched in Sec. 4.3: a
+// parallel permutation of whole blocks, then closing the gaps the partial blocks
+// leave).  Three steps:
+//
+//  F1  block permutation.  Logical block L moves to physical block
+//      rot(L) = (L + sigma) mod n_pi: logical sigma .. sigma + floor(n/b) - 1 land
+//      on the A blocks in order (their homes, as in Alg. 7 under reading G2) and
+//      the at most sigma allocated blocks after them land in T.  The content of
+//      physical p moves to next(p) = rot(pi^-1[p]), a permutation of the n_pi
+//      physical blocks.  Its cycles are found by pointer jumping: after
+//      ceil(log2 n_pi) doubling steps every node knows the smallest node of its
+//      cycle (the leader) and its distance to it, hence its rank in the cycle and
+//      the cycle length.  Nodes of cycles longer than one are laid out in an
+//      order array, cycle after cycle by rank, and cut into jobs of S nodes.  A
+//      job moves its nodes in decreasing rank (each node receives its
+//      predecessor's content after its own content was read); the first node of
+//      a piece of a cycle that spans jobs is saved to a temporary block first.
+//      Jobs are split further by columns of the blocks.  Unallocated blocks
+//      carry no data and are not copied.
+//  F2  ordered compaction.  A block j then holds logical sigma + j; its used
+//      elements move left by G_j, the unused tails of the partial blocks before
+//      it (non-decreasing in j).  Chunks run in increasing dynamic order; a
+//      chunk writes only after every chunk whose source its destination
+//      overlaps has loaded.
+//  F3  the blocks in T are copied to the end of A.
+#pragma once
+
+#include "common.hpp"
+
+namespace rs {
+
+constexpr uint32_t kFinJob = 1024;      // nodes per job of F1
+constexpr uint32_t kFinCols = 256;      // columns of a block moved by one F1 workgroup
+constexpr uint32_t kFinDepth = 8;       // loads in flight per thread in F1
+constexpr uint32_t kScanTile = 4096;    // elements per workgroup of the device scan
+constexpr uint32_t kGarbage = 0x80000000u;
+
+inline uint64_t fin_align(uint64_t x) { return (x + 255) / 256 * 256; }
+
+// Bytes of finalize scratch: eight n_pi-word arrays, the scan's block sums, the
+// F2 chunk flags and two temporary blocks per F1 job.
+constexpr uint32_t kCompactMin = 4096;  // smallest F2 chunk (elements)
+
+// F2 chunk flags (one per chunk) plus a counter
+inline uint64_t fin_flag_words(uint32_t npi, uint64_t n)
+{
+    return std::max<uint64_t>(npi, n / kCompactMin + 1) + 16;
+}
+
+inline uint64_t fin_scratch_bytes(uint32_t npi, uint64_t n, uint32_t b, uint32_t elem_bytes)
+{
+    uint64_t jobs = (npi + kFinJob - 1) / kFinJob;
+    uint64_t sums = (npi + kScanTile - 1) / kScanTile + 1;
+    return 8 * fin_align(4ull * npi) + fin_align(4 * sums) + fin_align(4 * fin_flag_words(npi, n)) +
+           fin_align(2 * jobs * (uint64_t)b * elem_bytes);
+}
+
+template <int KB, int VB>
+struct FinArgs {
+    using K = typename UInt<KB>::T;
+    using V = typename Payload<VB>::T;
+    K* Ak;
+    V* Av;
+    K* Tk;
+    V* Tv;
+    uint32_t* pi;
+    const uint32_t* Pidx;
+    const uint32_t* Plen;
+    const uint32_t* f;
+    uint64_t n;
+    uint32_t sigma, log2b, npi;
+    uint32_t* err;
+    uint8_t* scratch;
+    uint32_t* spare_pi;
+};
+
+struct FinArrays {
+    uint32_t *nxt, *j0, *j1, *v0, *v1, *o0, *o1, *ord, *sums, *flags;
+    uint64_t nflags;
+    uint8_t* temps;
+};
+
+inline FinArrays fin_arrays(uint8_t* s, uint32_t npi, uint64_t n)
+{
+    FinArrays a;
+    uint64_t w = fin_align(4ull * npi);
+    a.nxt = (uint32_t*)(s + 0 * w);
+    a.j0 = (uint32_t*)(s + 1 * w);
+    a.j1 = (uint32_t*)(s + 2 * w);
+    a.v0 = (uint32_t*)(s + 3 * w);
+    a.v1 = (uint32_t*)(s + 4 * w);
+    a.o0 = (uint32_t*)(s + 5 * w);
+    a.o1 = (uint32_t*)(s + 6 * w);
+    a.ord = (uint32_t*)(s + 7 * w);
+    a.sums = (uint32_t*)(s + 8 * w);
+    uint64_t sums = (npi + kScanTile - 1) / kScanTile + 1;
+    a.flags = (uint32_t*)(s + 8 * w + fin_align(4 * sums));
+    a.nflags = fin_flag_words(npi, n);
+    a.temps = s + 8 * w + fin_align(4 * sums) + fin_align(4 * a.nflags);
+    return a;
+}
+
+// ---- F1: cycles of next(p) ----------------------------------------------------------
+
+// next(pi[L]) = rot(L); the top bit marks a node whose content is unallocated.
+// Doubling state: J = next, (V, O) = (p, 0).
+__global__ void k_fin_init(const uint32_t* __restrict__ pi, const uint32_t* __restrict__ f_ptr,
+                           uint32_t sigma, uint32_t npi, uint32_t* __restrict__ nxt,
+                           uint32_t* __restrict__ J, uint32_t* __restrict__ V,
+                           uint32_t* __restrict__ O)
+{
+    const uint32_t f = *f_ptr;
+    for (uint32_t L = blockIdx.x * blockDim.x + threadIdx.x; L < npi;
+         L += gridDim.x * blockDim.x) {
+        const uint32_t p = pi[L];
+        if (p >= npi) continue;  // never for a permutation
+        const uint32_t to = L + sigma < npi ? L + sigma : L + sigma - npi;
+        const bool garbage = L < sigma || L >= f;
+        nxt[p] = to | (garbage ? kGarbage : 0u);
+        J[p] = to;
+        V[p] = p;
+        O[p] = 0;
+    }
+}
+
+// One doubling step: the window of 2^k successors becomes 2^(k+1).  (V, O) is
+// the smallest node in the window and the distance to its first occurrence.
+__global__ void k_fin_jump(const uint32_t* __restrict__ Ji, const uint32_t* __restrict__ Vi,
+                           const uint32_t* __restrict__ Oi, uint32_t* __restrict__ Jo,
+                           uint32_t* __restrict__ Vo, uint32_t* __restrict__ Oo, uint32_t npi,
+                           uint32_t window)
+{
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npi;
+         p += gridDim.x * blockDim.x) {
+        uint32_t q = Ji[p];
+        if (q >= npi) q = p;  // never for a permutation
+        uint32_t v = Vi[p], o = Oi[p];
+        const uint32_t v2 = Vi[q];
+        if (v2 < v) {
+            v = v2;
+            o = Oi[q] + window;
+        }
+        Vo[p] = v;
+        Oo[p] = o;
+        Jo[p] = Ji[q];
+    }
+}
+
+// rank of p in its cycle (0 at the leader) and the cycle length; the scan input
+// is the cycle length at leaders of cycles longer than one.
+__global__ void k_fin_rank(const uint32_t* __restrict__ nxt, const uint32_t* __restrict__ V,
+                           const uint32_t* __restrict__ O, uint32_t* __restrict__ rank,
+                           uint32_t* __restrict__ clen, uint32_t* __restrict__ scan_in,
+                           uint32_t npi)
+{
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npi;
+         p += gridDim.x * blockDim.x) {
+        const uint32_t l = V[p] < npi ? V[p] : p;
+        const uint32_t ln = nxt[l] & ~kGarbage;
+        const uint32_t len = ln == l ? 1u : O[ln] + 1u;
+        rank[p] = p == l ? 0u : len - O[p];
+        clen[p] = len;
+        scan_in[p] = (p == l && len > 1) ? len : 0u;
+    }
+}
+
+__global__ void k_fin_order(const uint32_t* __restrict__ nxt, const uint32_t* __restrict__ V,
+                            const uint32_t* __restrict__ rank, const uint32_t* __restrict__ clen,
+                            const uint32_t* __restrict__ base, uint32_t* __restrict__ ord,
+                            uint32_t npi)
+{
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npi;
+         p += gridDim.x * blockDim.x) {
+        if (clen[p] > 1 && V[p] < npi) {
+            const uint32_t at = base[V[p]] + rank[p];
+            if (at < npi) ord[at] = p | (nxt[p] & kGarbage);
+        }
+    }
+}
+
+// ---- device exclusive scan of n_pi words (three passes) ------------------------------
+
+__global__ __launch_bounds__(256) void k_scan_tiles(uint32_t* a, uint32_t count, uint32_t* sums)
+{
+    __shared__ uint32_t s[kScanTile];
+    __shared__ uint32_t tmp[5];
+    const uint32_t base = blockIdx.x * kScanTile;
+    for (uint32_t i = threadIdx.x; i < kScanTile; i += 256)
+        s[i] = base + i < count ? a[base + i] : 0u;
+    __syncthreads();
+    uint32_t total = block_excl_scan<256>(s, kScanTile, tmp);
+    for (uint32_t i = threadIdx.x; i < kScanTile; i += 256)
+        if (base + i < count) a[base + i] = s[i];
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(uint32_t* sums, uint32_t count)
+{
+    __shared__ uint32_t tmp[5];
+    __shared__ uint32_t s[kScanTile];
+    // count <= kScanTile: n_pi < 2^24 words per scan tile level is enough here
+    for (uint32_t i = threadIdx.x; i < kScanTile; i += 256) s[i] = i < count ? sums[i] : 0u;
+    __syncthreads();
+    uint32_t total = block_excl_scan<256>(s, kScanTile, tmp);
+    for (uint32_t i = threadIdx.x; i < count; i += 256) sums[i] = s[i];
+    if (threadIdx.x == 0) sums[count] = total;
+}
+
+__global__ void k_scan_add(uint32_t* a, uint32_t count, const uint32_t* sums)
+{
+    const uint32_t add = sums[blockIdx.x];
+    const uint32_t base = blockIdx.x * kScanTile;
+    for (uint32_t i = threadIdx.x; i < kScanTile; i += blockDim.x)
+        if (base + i < count) a[base + i] += add;
+}
+
+// ---- F1 jobs ---------------------------------------------------------------------------
+
+// The pieces of job j whose first node is overwritten by another job: the piece
+// at the job start (slot 2j) and the last piece if it starts inside the job and
+// continues after it (slot 2j + 1).  Returns the node (with garbage bit) or ~0.
+__device__ __forceinline__ void job_heads(const uint32_t* ord, const uint32_t* rank,
+                                          const uint32_t* clen, uint32_t j, uint32_t M,
+                                          uint32_t npi, uint32_t& h0, uint32_t& h1)
+{
+    const uint32_t i0 = j * kFinJob, i1 = min(M, i0 + kFinJob);
+    h0 = h1 = ~0u;
+    if (i1 <= i0) return;
+    const uint32_t p0 = ord[i0] & ~kGarbage;
+    const uint32_t pl0 = ord[i1 - 1] & ~kGarbage;
+    if (p0 >= npi || pl0 >= npi) return;
+    const uint32_t b0 = i0 - rank[p0];
+    if (rank[p0] != 0 || b0 + clen[p0] > i1) h0 = ord[i0];
+    const uint32_t pl = ord[i1 - 1] & ~kGarbage;
+    const uint32_t bl = (i1 - 1) - rank[pl];
+    if (bl > i0 && bl < i1 && bl + clen[pl] > i1) h1 = ord[bl];
+}
+
+template <typename X>
+__device__ __forceinline__ void copy_block_cols(X* dst, const X* src, uint32_t b)
+{
+    for (uint32_t c = threadIdx.x; c < b; c += blockDim.x) dst[c] = src[c];
+}
+
+// Saves the first node of every piece that another job overwrites.
+template <int KB, int VB>
+__global__ __launch_bounds__(256) void k_fin_save(FinArgs<KB, VB> a, FinArrays f,
+                                                  const uint32_t* rank, const uint32_t* clen,
+                                                  const uint32_t* M_ptr)
+{
+    using K = typename UInt<KB>::T;
+    using V = typename Payload<VB>::T;
+    const uint32_t M = min(*M_ptr, a.npi), j = blockIdx.x, b = 1u << a.log2b;
+    const uint32_t two_sigma = 2 * a.sigma;
+    if (j * kFinJob >= M) return;
+    uint32_t h[2];
+    job_heads(f.ord, rank, clen, j, M, a.npi, h[0], h[1]);
+    K* tk = (K*)f.temps;
+    V* tv = (V*)(f.temps + 2ull * ((a.npi + kFinJob - 1) / kFinJob) * b * KB);
+    for (int s = 0; s < 2; s++) {
+        if (h[s] == ~0u || (h[s] & kGarbage)) continue;
+        if (h[s] >= a.npi) {  // never for a consistent order array
+            if (threadIdx.x == 0) raise_error(a.err, kErrBounds);
+            continue;
+        }
+        const uint64_t slot = 2ull * j + s;
+        copy_block_cols(tk + (slot << a.log2b), blockat(a.Ak, a.Tk, h[s], two_sigma, a.log2b), b);
+        if constexpr (VB != 0)
+            copy_block_cols(tv + (slot << a.log2b), blockat(a.Av, a.Tv, h[s], two_sigma, a.log2b), b);
+    }
+}
+
+// Moves one column slice of one job: grid = jobs x (b / kFinCols).
+template <int KB, int VB>
+__global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArrays f,
+                                                      const uint32_t* rank, const uint32_t* clen,
+                                                      const uint32_t* M_ptr)
+{
+    using K = typename UInt<KB>::T;
+    using V = typename Payload<VB>::T;
+    const uint32_t M = min(*M_ptr, a.npi), j = blockIdx.x, b = 1u << a.log2b;
+    const uint32_t two_sigma = 2 * a.sigma;
+    const uint32_t i0 = j * kFinJob;
+    if (i0 >= M) return;
+    const uint32_t i1 = min(M, i0 + kFinJob);
+    const uint32_t col = blockIdx.y * kFinCols + threadIdx.x;
+    const bool active = col < b;
+    const uint32_t log2b = a.log2b;
+    uint32_t h[2];
+    job_heads(f.ord, rank, clen, j, M, a.npi, h[0], h[1]);
+    const K* tk = (const K*)f.temps;
+    const V* tv = (const V*)(f.temps + 2ull * ((a.npi + kFinJob - 1) / kFinJob) * b * KB);
+
+    // node ids come from the order array; an id outside [0, n_pi) is clamped to a
+    // T block (only possible for a corrupt state, which also raises an error)
+    auto safe = [&](uint32_t node) { return node < a.npi ? node : 0u; };
+    auto addr_k = [&](uint32_t node) { return blockat(a.Ak, a.Tk, safe(node), two_sigma, log2b) + col; };
+    auto addr_v = [&](uint32_t node) { return blockat(a.Av, a.Tv, safe(node), two_sigma, log2b) + col; };
+
+    uint32_t i = i0;
+    while (i < i1) {
+        const uint32_t p = f.ord[i] & ~kGarbage;
+        if (p >= a.npi) {  // never for a consistent order array
+            if (threadIdx.x == 0) raise_error(a.err, kErrBounds);
+            return;
+        }
+        const uint32_t r = rank[p], L = clen[p], cb = i - r;  // cycle base in ord
+        if (r >= L || cb + L > M) {
+            if (threadIdx.x == 0) raise_error(a.err, kErrBounds);
+            return;
+        }
+        const uint32_t e = min(i1, cb + L);                   // piece covers ord[i .. e)
+        const uint32_t ra = r, rb = r + (e - i);
+        const bool whole = ra == 0 && rb == L;
+        // the head's content: from a register (whole cycle) or a saved block
+        K hk{};
+        V hv{};
+        const uint32_t head = f.ord[i];
+        const bool head_garbage = head & kGarbage;
+        if (active && !head_garbage) {
+            if (whole) {
+                hk = *addr_k(head & ~kGarbage);
+                if constexpr (VB != 0) hv = *addr_v(head & ~kGarbage);
+            } else {
+                const uint64_t slot = 2ull * j + (i == i0 ? 0 : 1);
+                hk = tk[(slot << log2b) + col];
+                if constexpr (VB != 0) hv = tv[(slot << log2b) + col];
+            }
+        }
+        // node(x + 1 mod L) <- node(x) for x = rb-1 down to ra+1, in batches
+        uint32_t x = rb;  // next source rank + 1
+        while (x > ra + 1) {
+            const uint32_t cnt = min(kFinDepth, x - (ra + 1));
+            K bk[kFinDepth];
+            V bv[kFinDepth];
+            uint32_t src[kFinDepth + 1];
+#pragma unroll
+            for (uint32_t u = 0; u < kFinDepth; u++) {
+                if (u < cnt) {
+                    src[u] = f.ord[cb + x - 1 - u];
+                    if (active && !(src[u] & kGarbage)) {
+                        bk[u] = *addr_k(src[u] & ~kGarbage);
+                        if constexpr (VB != 0) bv[u] = *addr_v(src[u] & ~kGarbage);
+                    }
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kFinDepth; u++) {
+                if (u < cnt) {
+                    const uint32_t rd = x - u;  // destination rank (mod L)
+                    const uint32_t dst = f.ord[cb + (rd == L ? 0 : rd)] & ~kGarbage;
+                    if (active && !(src[u] & kGarbage)) {
+                        *addr_k(dst) = bk[u];
+                        if constexpr (VB != 0) *addr_v(dst) = bv[u];
+                    }
+                }
+            }
+            x -= cnt;
+        }
+        // node(ra + 1 mod L) <- head
+        {
+            const uint32_t rd = ra + 1;
+            const uint32_t dst = f.ord[cb + (rd == L ? 0 : rd)] & ~kGarbage;
+            if (active && !head_garbage) {
+                *addr_k(dst) = hk;
+                if constexpr (VB != 0) *addr_v(dst) = hv;
+            }
+        }
+        i = e;
+    }
+}
+
+// ---- F2: ordered compaction -----------------------------------------------------------
+
+// gap[i] = sum of (b - len) over partial entries 0 .. i-1 of P; gap[sigma] = total
+__global__ __launch_bounds__(256) void k_fin_gaps(const uint32_t* Pidx, const uint32_t* Plen,
+                                                  uint32_t sigma, uint32_t log2b, uint32_t npi,
+                                                  uint32_t* gap)
+{
+    extern __shared__ uint32_t s[];
+    __shared__ uint32_t tmp[5];
+    const uint32_t b = 1u << log2b;
+    for (uint32_t i = threadIdx.x; i < sigma; i += 256) s[i] = Pidx[i] < npi ? b - Plen[i] : 0u;
+    __syncthreads();
+    uint32_t total = block_excl_scan<256>(s, sigma, tmp);
+    for (uint32_t i = threadIdx.x; i < sigma; i += 256) gap[i] = s[i];
+    if (threadIdx.x == 0) gap[sigma] = total;
+}
+
+// Unused elements before logical block L and the length of L.
+__device__ __forceinline__ void gap_before(const uint32_t* Pidx, const uint32_t* Plen,
+                                           const uint32_t* gap, uint32_t sigma, uint32_t L,
+                                           uint32_t b, uint32_t& G, uint32_t& len)
+{
+    uint32_t lo = 0, hi = sigma;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (Pidx[mid] < L) lo = mid + 1;
+        else hi = mid;
+    }
+    G = gap[lo];
+    len = (lo < sigma && Pidx[lo] == L) ? Plen[lo] : b;
+}
+
+// One chunk = CHUNK consecutive element positions of the A blocks (whole blocks,
+// or a part of one block when b > CHUNK), staged in LDS.
+template <int KB, int VB, int CHUNK>
+__global__ __launch_bounds__(256) void k_fin_compact(FinArgs<KB, VB> a, const uint32_t* gap,
+                                                     uint32_t* flags, uint32_t* ctr)
+{
+    using K = typename UInt<KB>::T;
+    using V = typename Payload<VB>::T;
+    constexpr uint32_t MAXB = CHUNK / 64;
+    __shared__ K sk[CHUNK];
+    __shared__ V sv[VB ? CHUNK : 1];
+    __shared__ uint32_t bG[MAXB], bL[MAXB];
+    __shared__ uint32_t s_chunk;
+    const uint32_t tid = threadIdx.x, b = 1u << a.log2b, sigma = a.sigma, log2b = a.log2b;
+    const uint64_t total = (a.n >> log2b) << log2b;  // positions of the full A blocks
+    if (tid == 0) s_chunk = add_agent(ctr, 1u);
+    __syncthreads();
+    const uint32_t c = s_chunk;
+    const uint64_t p0 = (uint64_t)c * CHUNK;
+    if (p0 >= total) return;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(CHUNK, total - p0);
+    const uint64_t j0 = p0 >> log2b;
+    const uint32_t nblk = (uint32_t)(((p0 + cnt - 1) >> log2b) - j0 + 1);
+    for (uint32_t i = tid; i < nblk; i += 256) {
+        uint32_t G, len;
+        gap_before(a.Pidx, a.Plen, gap, sigma, sigma + (uint32_t)(j0 + i), b, G, len);
+        bG[i] = G;
+        bL[i] = len;
+    }
+    __syncthreads();
+    if (bG[nblk - 1] == 0) {  // no gap before this chunk: it stays where it is
+        if (tid == 0) st_agent(flags + c, 1u);
+        return;
+    }
+    // load (elements beyond a block's length are never read)
+    for (uint32_t i = tid; i < cnt; i += 256) {
+        const uint64_t pos = p0 + i;
+        const uint32_t jb = (uint32_t)((pos >> log2b) - j0), off = (uint32_t)pos & (b - 1);
+        if (off < bL[jb]) {
+            sk[i] = a.Ak[pos];
+            if constexpr (VB != 0) sv[i] = a.Av[pos];
+        }
+    }
+    __syncthreads();
+    if (tid == 0) st_agent(flags + c, 1u);
+    // wait for the chunks whose sources overlap the destination
+    const uint64_t dst0 = p0 - bG[0];
+    const uint32_t cfirst = (uint32_t)(dst0 / CHUNK);
+    for (uint32_t w = cfirst + tid; w < c; w += 256) {
+        uint32_t spins = 0;
+        while (ld_agent(flags + w) == 0u) {
+            if (++spins > kSpinLimit || ld_agent(a.err)) { raise_error(a.err, kErrSpin); break; }
+            spin_pause();
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt; i += 256) {
+        const uint64_t pos = p0 + i;
+        const uint32_t jb = (uint32_t)((pos >> log2b) - j0), off = (uint32_t)pos & (b - 1);
+        if (off < bL[jb]) {
+            const uint64_t dst = pos - bG[jb];
+            a.Ak[dst] = sk[i];
+            if constexpr (VB != 0) a.Av[dst] = sv[i];
+        }
+    }
+}
+
+// ---- F3: blocks resident in T ------------------------------------------------------
+
+template <int KB, int VB>
+__global__ __launch_bounds__(256) void k_fin_tail(FinArgs<KB, VB> a, const uint32_t* gap)
+{
+    const uint32_t sigma = a.sigma, b = 1u << a.log2b, nb = (uint32_t)(a.n >> a.log2b);
+    const uint32_t L = sigma + nb + blockIdx.x;
+    if (L >= *a.f || L >= a.npi) return;
+    uint32_t G, len;
+    gap_before(a.Pidx, a.Plen, gap, sigma, L, b, G, len);
+    const uint32_t phys = L + sigma - a.npi;  // rot(L) for L >= n_pi - sigma
+    const uint64_t dst = ((uint64_t)(L - sigma) << a.log2b) - G;
+    if (dst + len > a.n) {  // never for a consistent state
+        raise_error(a.err, kErrBounds);
+        return;
+    }
+    for (uint32_t i = threadIdx.x; i < len; i += 256) {
+        a.Ak[dst + i] = a.Tk[((uint64_t)phys << a.log2b) + i];
+        if constexpr (VB != 0) a.Av[dst + i] = a.Tv[((uint64_t)phys << a.log2b) + i];
+    }
+}
+
+// ---- host launch sequence ----------------------------------------------------------
+
+inline void fin_scan(uint32_t* a, uint32_t count, uint32_t* sums, hipStream_t s)
+{
+    const uint32_t tiles = (count + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(256), 0, s, a, count, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, sums, tiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(256), 0, s, a, count, sums);
+}
+
+template <int KB, int VB>
+int finalize_parallel(FinArgs<KB, VB>& a, hipStream_t s)
+{
+    const uint32_t npi = a.npi, b = 1u << a.log2b;
+    FinArrays f = fin_arrays(a.scratch, npi, a.n);
+    const uint32_t grid = std::min<uint32_t>((npi + 255) / 256, 8192);
+    // F1: cycles
+    uint32_t *J[2] = {f.j0, f.j1}, *Vv[2] = {f.v0, f.v1}, *O[2] = {f.o0, f.o1};
+    hipLaunchKernelGGL(k_fin_init, dim3(grid), dim3(256), 0, s, a.pi, a.f, a.sigma, npi, f.nxt,
+                       J[0], Vv[0], O[0]);
+    int cur = 0;
+    for (uint64_t w = 1; w < npi; w <<= 1) {
+        hipLaunchKernelGGL(k_fin_jump, dim3(grid), dim3(256), 0, s, J[cur], Vv[cur], O[cur],
+                           J[cur ^ 1], Vv[cur ^ 1], O[cur ^ 1], npi, (uint32_t)w);
+        cur ^= 1;
+    }
+    uint32_t* V = Vv[cur];
+    uint32_t* Ofin = O[cur];
+    uint32_t* rank = J[0];
+    uint32_t* clen = J[1];
+    uint32_t* scan = Vv[cur ^ 1];
+    hipLaunchKernelGGL(k_fin_rank, dim3(grid), dim3(256), 0, s, f.nxt, V, Ofin, rank, clen, scan,
+                       npi);
+    fin_scan(scan, npi, f.sums, s);
+    const uint32_t tiles = (npi + kScanTile - 1) / kScanTile;
+    const uint32_t* M_ptr = f.sums + tiles;  // total number of nodes to move
+    hipLaunchKernelGGL(k_fin_order, dim3(grid), dim3(256), 0, s, f.nxt, V, rank, clen, scan,
+                       f.ord, npi);
+    const uint32_t jobs = (npi + kFinJob - 1) / kFinJob;
+    hipLaunchKernelGGL((k_fin_save<KB, VB>), dim3(jobs), dim3(256), 0, s, a, f, rank, clen, M_ptr);
+    const uint32_t slices = (b + kFinCols - 1) / kFinCols;
+    hipLaunchKernelGGL((k_fin_move<KB, VB>), dim3(jobs, slices), dim3(kFinCols), 0, s, a, f, rank,
+                       clen, M_ptr);
+    // F2: compaction (gap prefix in f.j0 is free again: rank is dead after the moves)
+    uint32_t* gap = Ofin;  // free after k_fin_order
+    hipLaunchKernelGGL(k_fin_gaps, dim3(1), dim3(256), 4 * a.sigma, s, a.Pidx, a.Plen, a.sigma,
+                       a.log2b, npi, gap);
+    const uint64_t positions = (a.n >> a.log2b) << a.log2b;
+    constexpr int CHUNK = (KB + VB >= 12) ? kCompactMin : 2 * kCompactMin;
+    const uint32_t chunks = (uint32_t)((positions + CHUNK - 1) / CHUNK);
+    uint32_t* ctr = f.flags + (f.nflags - 1);  // counter after the flags
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
+                       dim3(256), 0, s, f.flags, f.nflags, 0u);
+    if (chunks)
+        hipLaunchKernelGGL((k_fin_compact<KB, VB, CHUNK>), dim3(chunks), dim3(256), 0, s, a, gap,
+                           f.flags, ctr);
+    // F3: the blocks in T
+    hipLaunchKernelGGL((k_fin_tail<KB, VB>), dim3(a.sigma), dim3(256), 0, s, a, gap);
+    return 0;
+}
+
+}  // namespace rs

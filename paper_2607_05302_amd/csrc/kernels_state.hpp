@@ -1,0 +1,153 @@
+// State kernels of Radsort: fills, the up-front digit histograms, the per-round
+// plan (closed forms of C, S, P, f), setup (Alg. 4) and fixupPhase (Alg. 6).
+#pragma once
+
+#include "common.hpp"
+
+namespace rs {
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t v)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Histograms of every key position in one pass over the keys (the first loop
+// of Alg. 1, taken for all positions up front as the paper's "generic" variant
+// does, Sec. 5).  hist[t * sigma + c] counts key(x, t) = c, t = 0 the most
+// significant digit.  hist must be zero on entry.  Dynamic LDS: nt * sigma words.
+template <int KB>
+__global__ __launch_bounds__(256) void k_histograms(const typename UInt<KB>::T* __restrict__ keys,
+                                                    uint64_t n, uint32_t bits, uint32_t nt,
+                                                    uint32_t* __restrict__ hist)
+{
+    using K = typename UInt<KB>::T;
+    extern __shared__ uint32_t h[];
+    const uint32_t sigma = 1u << bits, mask = sigma - 1, words = nt * sigma;
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        K x = keys[i];
+        for (uint32_t t = 0; t < nt; t++) {
+            uint32_t d = (uint32_t)(x >> (bits * (nt - 1 - t))) & mask;
+            atomicAdd(&h[t * sigma + d], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// Everything the rounds need that follows from the histograms alone, by the
+// closed forms of Alg. 5 (eager allocation) and Alg. 6:
+//   C[d]   = 1 + floor(cnt_d / b)                     blocks of bucket d
+//   S[d]   = sigma + sum_{d' < d} C[d']               first logical block of d
+//   P[d]   = (S[d] + C[d] - 1, cnt_d mod b)           its partial block
+//   f      = sigma + sum_d C[d]
+//   est[d] = sum_{d' < d} cnt_d'                      element start (Alg. 1)
+// Round r sorts by key position t = nt-1-r.  P and f of index r describe the
+// input of round r; index 0 is the state after setup (Alg. 4).
+struct PlanPtrs {
+    uint32_t* S;     // [nt][sigma]
+    uint32_t* Pidx;  // [nt+1][sigma]
+    uint32_t* Plen;  // [nt+1][sigma]
+    uint32_t* f;     // [nt+1]
+    uint32_t* est;   // [nt][sigma]
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_plan(const uint32_t* __restrict__ hist, uint64_t n,
+                                            uint32_t log2b, uint32_t bits, uint32_t nt,
+                                            uint32_t npi, PlanPtrs p)
+{
+    extern __shared__ uint32_t sm[];
+    const uint32_t sigma = 1u << bits, b = 1u << log2b, tid = threadIdx.x;
+    uint32_t* C = sm;
+    uint32_t* E = sm + sigma;
+    uint32_t* tmp = sm + 2 * sigma;
+    const uint32_t nb = (uint32_t)(n >> log2b);
+    if (tid == 0) p.f[0] = sigma + nb + 1;
+    for (uint32_t d = tid; d < sigma; d += NT) {
+        p.Pidx[d] = d == 0 ? sigma + nb : npi;     // the input tail, then dummies
+        p.Plen[d] = d == 0 ? (uint32_t)(n & (b - 1)) : 0;
+    }
+    for (uint32_t r = 0; r < nt; r++) {
+        const uint32_t* cnt = hist + (nt - 1 - r) * sigma;
+        for (uint32_t d = tid; d < sigma; d += NT) {
+            C[d] = 1 + (cnt[d] >> log2b);
+            E[d] = cnt[d];
+        }
+        __syncthreads();
+        uint32_t total = block_excl_scan<NT>(C, sigma, tmp);
+        block_excl_scan<NT>(E, sigma, tmp);
+        for (uint32_t d = tid; d < sigma; d += NT) {
+            uint32_t c = 1 + (cnt[d] >> log2b);
+            uint32_t s = sigma + C[d];
+            p.S[r * sigma + d] = s;
+            p.Pidx[(r + 1) * sigma + d] = s + c - 1;
+            p.Plen[(r + 1) * sigma + d] = cnt[d] & (b - 1);
+            p.est[r * sigma + d] = E[d];
+        }
+        if (tid == 0) p.f[r + 1] = sigma + total;
+        __syncthreads();
+    }
+}
+
+// setup (Alg. 4): pi = [0..sigma) | 2 sigma .. sigma + f - 2 | sigma .. 2 sigma),
+// the n mod b tail of A copied to physical block sigma, the other pi buffer
+// cleared to "unset".
+template <int KB, int VB>
+__global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
+                        typename Payload<VB>::T* __restrict__ Av,
+                        typename UInt<KB>::T* __restrict__ Tk,
+                        typename Payload<VB>::T* __restrict__ Tv, uint64_t n, uint32_t log2b,
+                        uint32_t sigma, uint32_t npi, uint32_t* __restrict__ pi,
+                        uint32_t* __restrict__ pi_next)
+{
+    const uint64_t nb = n >> log2b, tail = n - (nb << log2b);
+    const uint32_t f = sigma + (uint32_t)nb + 1;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < npi || i < tail;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i < npi) {
+            uint32_t L = (uint32_t)i, v;
+            if (L < sigma) v = L;
+            else if (L + 1 < f) v = L + sigma;
+            else v = sigma + (L - (f - 1));
+            pi[L] = v;
+            pi_next[L] = kEmpty;
+        }
+        if (i < tail) {
+            uint64_t dst = ((uint64_t)sigma << log2b) + i;
+            Tk[dst] = Ak[(nb << log2b) + i];
+            if constexpr (VB != 0) Tv[dst] = Av[(nb << log2b) + i];
+        }
+    }
+}
+
+// fixupPhase (Alg. 6) after a sort round.  The sort round already wrote
+// pi_new[S[d] + q] for every block q >= 1 of every bucket (the blocks drawn when
+// a block filled).  Here: the first block of bucket d is pool entry d (the
+// initial newBucketBlock draws of Alg. 5), the head start is pool entries
+// c .. c + sigma - 1 and the rest keeps its place, with c = f_out - sigma the
+// number of blocks drawn.  Each entry of pi_old is read by the thread that owns
+// it, which then resets it to "unset" for the next round.
+__global__ void k_fixup(uint32_t* __restrict__ pi_old, uint32_t* __restrict__ pi_new,
+                        const uint32_t* __restrict__ S, const uint32_t* __restrict__ f_out,
+                        uint32_t sigma, uint32_t npi)
+{
+    const uint32_t c = *f_out - sigma;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < npi;
+         j += gridDim.x * blockDim.x) {
+        uint32_t v = pi_old[j];
+        if (j < sigma) {
+            if (S[j] < npi) pi_new[S[j]] = v;
+        }
+        else if (j >= c && j < c + sigma) pi_new[j - c] = v;
+        else if (j >= c + sigma) pi_new[j] = v;
+        pi_old[j] = kEmpty;
+    }
+}
+
+}  // namespace rs

@@ -1,0 +1,680 @@
+// Host side of the Radsort library: argument checks, workspace layout, the
+// launch sequence of Alg. 2 on a HIP stream, and the C ABI of include/radsort.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/radsort.h"
+#include "common.hpp"
+#include "kernels_state.hpp"
+#include "kernel_round.hpp"
+#include "kernels_finalize.hpp"
+#include "kernels_finalize_seq.hpp"
+
+using namespace rs;
+
+namespace {
+
+thread_local hipError_t g_last_hip = hipSuccess;
+radsort_stats g_stats{};
+
+#define RS_HIP(call)                                 \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) {                      \
+            g_last_hip = e_;                         \
+            return RADSORT_E_DEVICE;                 \
+        }                                            \
+    } while (0)
+
+constexpr uint32_t kRingWords = 1u << 19;  // look-back ring: ring_w * sigma status words
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+int ilog2(uint64_t x)
+{
+    int r = 0;
+    while ((1ull << r) < x) r++;
+    return r;
+}
+
+// Tile shape per element size: E = 64 * WAVES * ITEMS slots per workgroup.
+template <int KB, int VB> struct TileCfg {
+    static constexpr int WAVES = 4;
+    static constexpr int ITEMS = (KB + VB >= 12) ? 8 : 16;
+    static constexpr int E = 64 * WAVES * ITEMS;
+};
+
+struct Geo {
+    uint64_t n = 0;
+    uint32_t kb = 0, vb = 0, bits = 0, sigma = 0, nt = 0, b = 0, log2b = 0;
+    uint64_t nb = 0;
+    uint32_t npi = 0, E = 0, tiles = 0, ring_w = 0;
+};
+
+// Workspace regions (byte offsets), each 256-byte aligned.
+struct Layout {
+    uint64_t Tk, Tv, pi0, pi1, hist, S, Pidx, Plen, f, est, ctr, ring, fin, alt_k, alt_v;
+    uint64_t ring_bytes, fin_bytes, total;
+};
+
+uint32_t tile_elems(uint32_t kb, uint32_t vb)
+{
+    if (kb == 4 && vb == 0) return TileCfg<4, 0>::E;
+    if (kb == 4 && vb == 4) return TileCfg<4, 4>::E;
+    if (kb == 4 && vb == 8) return TileCfg<4, 8>::E;
+    if (kb == 8 && vb == 0) return TileCfg<8, 0>::E;
+    if (kb == 8 && vb == 4) return TileCfg<8, 4>::E;
+    return TileCfg<8, 8>::E;
+}
+
+int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bits,
+             const radsort_opts* opts)
+{
+    if (key_bytes != 4 && key_bytes != 8) return RADSORT_E_INVALID;
+    if (payload_bytes != 0 && payload_bytes != 4 && payload_bytes != 8) return RADSORT_E_INVALID;
+    if (digit_bits < 1 || digit_bits > 16) return RADSORT_E_INVALID;
+    if (digit_bits > 11) return RADSORT_E_UNSUPPORTED;
+    uint32_t b = (opts && opts->block_elems) ? opts->block_elems : 1024u;
+    if (b < 64 || b > 65536 || (b & (b - 1))) return RADSORT_E_INVALID;
+    if (n >= (1ull << 32)) return RADSORT_E_UNSUPPORTED;
+    g.n = n;
+    g.kb = key_bytes;
+    g.vb = payload_bytes;
+    g.bits = digit_bits;
+    g.sigma = 1u << digit_bits;
+    g.nt = (8 * key_bytes + digit_bits - 1) / digit_bits;
+    g.b = b;
+    g.log2b = ilog2(b);
+    g.nb = n >> g.log2b;
+    uint64_t npi = g.nb + 2ull * g.sigma;  // state table, Sec. 2.1
+    // pi entries are 32-bit with the top bit free; finalize scans at most 4096^2 entries
+    if (npi >= (uint64_t)kScanTile * kScanTile) return RADSORT_E_UNSUPPORTED;
+    g.npi = (uint32_t)npi;
+    g.E = tile_elems(g.kb, g.vb);
+    // input slots of a round: at most (floor(n/b) + sigma) blocks of b
+    uint64_t slots = (g.nb + g.sigma) << g.log2b;
+    g.tiles = (uint32_t)((slots + g.E - 1) / g.E);
+    g.ring_w = std::max<uint32_t>(256u, kRingWords / g.sigma);
+    return RADSORT_OK;
+}
+
+// Finalize scratch (parallel Alg. 7): see kernels_finalize.hpp.
+uint64_t finalize_bytes(const Geo& g) { return fin_scratch_bytes(g.npi, g.n, g.b, g.kb + g.vb); }
+
+Layout make_layout(const Geo& g, bool oop)
+{
+    Layout L{};
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    const uint64_t sig = g.sigma, nt = g.nt;
+    if (!oop) {
+        L.Tk = take(2 * sig * g.b * g.kb);
+        L.Tv = take(2 * sig * g.b * g.vb);
+        L.pi0 = take(4ull * g.npi);
+        L.pi1 = take(4ull * g.npi);
+    } else {
+        L.alt_k = take(g.n * g.kb);
+        L.alt_v = take(g.n * g.vb);
+    }
+    L.hist = take(4 * nt * sig);
+    L.S = take(4 * nt * sig);
+    L.Pidx = take(4 * (nt + 1) * sig);
+    L.Plen = take(4 * (nt + 1) * sig);
+    L.f = take(4 * (nt + 1));
+    L.est = take(4 * nt * sig);
+    L.ctr = take(4 * (nt + 8));
+    L.ring_bytes = 8ull * g.ring_w * sig;
+    L.fin_bytes = oop ? 0 : finalize_bytes(g);
+    L.ring = take(std::max(L.ring_bytes, L.fin_bytes));  // finalize reuses the ring
+    L.fin = L.ring;
+    L.total = o;
+    return L;
+}
+
+void launch_fill(uint32_t* p, uint64_t count, uint32_t v, hipStream_t s)
+{
+    if (!count) return;
+    uint32_t grid = (uint32_t)std::min<uint64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, s, p, count, v);
+}
+
+}  // namespace
+
+struct radsort_state {
+    Geo g;
+    Layout L;
+    uint8_t* ws = nullptr;
+    bool own_ws = false;
+    void* keys = nullptr;
+    void* vals = nullptr;
+    uint32_t rounds_done = 0;  // rounds since setup
+    uint64_t seq = 0;          // look-back ring sequence of the next round's tile 0
+    int cur = 0;               // which pi buffer holds pi
+    bool is_setup = false;
+
+    uint32_t* u32(uint64_t off) const { return (uint32_t*)(ws + off); }
+    uint32_t* pi(int which) const { return u32(which ? L.pi1 : L.pi0); }
+    PlanPtrs plan() const
+    {
+        return PlanPtrs{u32(L.S), u32(L.Pidx), u32(L.Plen), u32(L.f), u32(L.est)};
+    }
+    uint32_t* err() const { return u32(L.ctr) + g.nt; }
+    uint32_t* tile_ctr(uint32_t r) const { return u32(L.ctr) + r; }
+};
+
+namespace {
+
+// ---- launch helpers templated on key / payload widths --------------------------------
+
+template <int KB> int launch_histograms(const void* keys, const Geo& g, uint32_t* hist,
+                                        hipStream_t s)
+{
+    launch_fill(hist, (uint64_t)g.nt * g.sigma, 0, s);
+    if (g.n == 0) return RADSORT_OK;
+    const uint32_t lds = 4 * g.nt * g.sigma;
+    uint32_t grid = (uint32_t)std::min<uint64_t>((g.n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_histograms<KB>, dim3(grid), dim3(256), lds, s,
+                       (const typename UInt<KB>::T*)keys, g.n, g.bits, g.nt, hist);
+    return RADSORT_OK;
+}
+
+int launch_plan(const Geo& g, const uint32_t* hist, PlanPtrs p, hipStream_t s)
+{
+    const uint32_t lds = 4 * (2 * g.sigma + 8);
+    hipLaunchKernelGGL(k_plan<256>, dim3(1), dim3(256), lds, s, hist, g.n, g.log2b, g.bits,
+                       g.nt, g.npi, p);
+    return RADSORT_OK;
+}
+
+template <int KB, int VB, bool OOP>
+int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s)
+{
+    constexpr int W = TileCfg<KB, VB>::WAVES, I = TileCfg<KB, VB>::ITEMS;
+    const uint32_t grid = OOP ? (uint32_t)((g.n + g.E - 1) / g.E) : g.tiles;
+    if (grid == 0) return RADSORT_OK;
+    if (g.bits == 8)
+        hipLaunchKernelGGL((k_round<KB, VB, OOP, 8, 256, W, I>), dim3(grid), dim3(64 * W), 0, s, a);
+    else if (g.bits <= 8)
+        hipLaunchKernelGGL((k_round<KB, VB, OOP, 0, 256, W, I>), dim3(grid), dim3(64 * W), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_round<KB, VB, OOP, 0, 2048, W, I>), dim3(grid), dim3(64 * W), 0, s, a);
+    return RADSORT_OK;
+}
+
+template <int KB, int VB> struct Ops {
+    using K = typename UInt<KB>::T;
+    using V = typename Payload<VB>::T;
+
+    static int setup(radsort_state* st, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        launch_histograms<KB>(st->keys, g, st->u32(st->L.hist), s);
+        launch_plan(g, st->u32(st->L.hist), st->plan(), s);
+        launch_fill(st->u32(st->L.ctr), g.nt + 8, 0, s);
+        launch_fill((uint32_t*)(st->ws + st->L.ring), st->L.ring_bytes / 4, 0, s);
+        uint64_t work = std::max<uint64_t>(g.npi, g.n & (g.b - 1));
+        uint32_t grid = (uint32_t)std::min<uint64_t>((work + 255) / 256, 4096);
+        hipLaunchKernelGGL((k_setup<KB, VB>), dim3(grid), dim3(256), 0, s, (K*)st->keys,
+                           (V*)st->vals, (K*)(st->ws + st->L.Tk), (V*)(st->ws + st->L.Tv), g.n,
+                           g.log2b, g.sigma, g.npi, st->pi(0), st->pi(1));
+        st->cur = 0;
+        st->rounds_done = 0;
+        st->seq = 0;
+        st->is_setup = true;
+        return RADSORT_OK;
+    }
+
+    static int round(radsort_state* st, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        const uint32_t r = st->rounds_done;
+        const uint32_t t = g.nt - 1 - r;  // key position of this round
+        TileArgs<KB, VB> a{};
+        a.Ak = (K*)st->keys;
+        a.Av = (V*)st->vals;
+        a.Tk = (K*)(st->ws + st->L.Tk);
+        a.Tv = (V*)(st->ws + st->L.Tv);
+        a.pi_old = st->pi(st->cur);
+        a.pi_new = st->pi(st->cur ^ 1);
+        a.Pidx = st->u32(st->L.Pidx) + r * g.sigma;
+        a.Plen = st->u32(st->L.Plen) + r * g.sigma;
+        a.f_in = st->u32(st->L.f) + r;
+        a.S = st->u32(st->L.S) + r * g.sigma;
+        a.ring = (uint64_t*)(st->ws + st->L.ring);
+        a.tile_ctr = st->tile_ctr(r);
+        a.err = st->err();
+        a.seq_base = st->seq;
+        a.shift = g.bits * (g.nt - 1 - t);
+        a.bits = g.bits;
+        a.log2b = g.log2b;
+        a.npi = g.npi;
+        a.ring_w = g.ring_w;
+        launch_fill(a.tile_ctr, 1, 0, s);
+        launch_round_t<KB, VB, false>(g, a, s);
+        uint32_t grid = (uint32_t)std::min<uint64_t>((g.npi + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_fixup, dim3(grid), dim3(256), 0, s, st->pi(st->cur),
+                           st->pi(st->cur ^ 1), a.S, st->u32(st->L.f) + r + 1, g.sigma, g.npi);
+        st->cur ^= 1;
+        st->rounds_done++;
+        st->seq += g.tiles;
+        return RADSORT_OK;
+    }
+
+    static int finalize_seq(radsort_state* st, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        const uint32_t r = st->rounds_done;
+        hipLaunchKernelGGL((k_finalize_seq<KB, VB, 1024>), dim3(1), dim3(1024), 0, s,
+                           (K*)st->keys, (V*)st->vals, (K*)(st->ws + st->L.Tk),
+                           (V*)(st->ws + st->L.Tv), st->pi(st->cur), st->u32(st->L.fin),
+                           st->u32(st->L.Pidx) + r * g.sigma, st->u32(st->L.Plen) + r * g.sigma,
+                           st->u32(st->L.f) + r, g.n, g.sigma, g.log2b, g.npi);
+        return RADSORT_OK;
+    }
+
+    static int finalize(radsort_state* st, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        const uint32_t r = st->rounds_done;
+        FinArgs<KB, VB> a{};
+        a.Ak = (K*)st->keys;
+        a.Av = (V*)st->vals;
+        a.Tk = (K*)(st->ws + st->L.Tk);
+        a.Tv = (V*)(st->ws + st->L.Tv);
+        a.pi = st->pi(st->cur);
+        a.Pidx = st->u32(st->L.Pidx) + r * g.sigma;
+        a.Plen = st->u32(st->L.Plen) + r * g.sigma;
+        a.f = st->u32(st->L.f) + r;
+        a.n = g.n;
+        a.sigma = g.sigma;
+        a.log2b = g.log2b;
+        a.npi = g.npi;
+        a.err = st->err();
+        a.scratch = st->ws + st->L.fin;
+        a.spare_pi = st->pi(st->cur ^ 1);
+        return finalize_parallel<KB, VB>(a, s);
+    }
+
+    static int logical(radsort_state* st, void* ok, void* ov, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        const uint32_t r = st->rounds_done;
+        const uint32_t grid = g.npi - g.sigma;
+        hipLaunchKernelGGL((k_gather_logical<KB, VB, 256>), dim3(grid), dim3(256), 0, s,
+                           (const K*)st->keys, (const V*)st->vals,
+                           (const K*)(st->ws + st->L.Tk), (const V*)(st->ws + st->L.Tv),
+                           st->pi(st->cur), st->u32(st->L.Pidx) + r * g.sigma,
+                           st->u32(st->L.Plen) + r * g.sigma, st->u32(st->L.f) + r, g.sigma,
+                           g.log2b, g.npi, (K*)ok, (V*)ov);
+        return RADSORT_OK;
+    }
+
+    // Alg. 1 rounds, ping-ponging between the caller's arrays and the workspace
+    static int oop_sort(void* keys, void* vals, const Geo& g, const Layout& L, uint8_t* ws,
+                        hipStream_t s)
+    {
+        uint32_t* hist = (uint32_t*)(ws + L.hist);
+        PlanPtrs p{(uint32_t*)(ws + L.S), (uint32_t*)(ws + L.Pidx), (uint32_t*)(ws + L.Plen),
+                   (uint32_t*)(ws + L.f), (uint32_t*)(ws + L.est)};
+        launch_histograms<KB>(keys, g, hist, s);
+        launch_plan(g, hist, p, s);
+        uint32_t* ctr = (uint32_t*)(ws + L.ctr);
+        launch_fill(ctr, g.nt + 8, 0, s);
+        launch_fill((uint32_t*)(ws + L.ring), L.ring_bytes / 4, 0, s);
+        K* bk[2] = {(K*)keys, (K*)(ws + L.alt_k)};
+        V* bv[2] = {(V*)vals, (V*)(ws + L.alt_v)};
+        const uint32_t tiles = (uint32_t)((g.n + g.E - 1) / g.E);
+        for (uint32_t r = 0; r < g.nt; r++) {
+            const uint32_t t = g.nt - 1 - r, from = r & 1;
+            TileArgs<KB, VB> a{};
+            a.Ak = bk[from];
+            a.Av = bv[from];
+            a.Tk = bk[from ^ 1];
+            a.Tv = bv[from ^ 1];
+            a.est = p.est + r * g.sigma;
+            a.n = g.n;
+            a.ring = (uint64_t*)(ws + L.ring);
+            a.tile_ctr = ctr + r;
+            a.err = ctr + g.nt;
+            a.seq_base = (uint64_t)r * tiles;
+            a.shift = g.bits * (g.nt - 1 - t);
+            a.bits = g.bits;
+            a.log2b = g.log2b;
+            a.ring_w = g.ring_w;
+            launch_round_t<KB, VB, true>(g, a, s);
+        }
+        if (g.nt & 1) {  // the result is in the workspace buffer: copy it back
+            RS_HIP(hipMemcpyAsync(keys, bk[1], g.n * KB, hipMemcpyDeviceToDevice, s));
+            if (VB) RS_HIP(hipMemcpyAsync(vals, bv[1], g.n * VB, hipMemcpyDeviceToDevice, s));
+        }
+        return RADSORT_OK;
+    }
+};
+
+template <template <int, int> class F, typename... Args>
+int dispatch(uint32_t kb, uint32_t vb, Args&&... args)
+{
+    if (kb == 4 && vb == 0) return F<4, 0>::run(args...);
+    if (kb == 4 && vb == 4) return F<4, 4>::run(args...);
+    if (kb == 4 && vb == 8) return F<4, 8>::run(args...);
+    if (kb == 8 && vb == 0) return F<8, 0>::run(args...);
+    if (kb == 8 && vb == 4) return F<8, 4>::run(args...);
+    if (kb == 8 && vb == 8) return F<8, 8>::run(args...);
+    return RADSORT_E_INVALID;
+}
+
+template <int KB, int VB> struct DoSetup {
+    static int run(radsort_state* st, hipStream_t s) { return Ops<KB, VB>::setup(st, s); }
+};
+template <int KB, int VB> struct DoRound {
+    static int run(radsort_state* st, hipStream_t s) { return Ops<KB, VB>::round(st, s); }
+};
+template <int KB, int VB> struct DoFinalize {
+    static int run(radsort_state* st, hipStream_t s) { return Ops<KB, VB>::finalize(st, s); }
+};
+template <int KB, int VB> struct DoFinalizeSeq {
+    static int run(radsort_state* st, hipStream_t s) { return Ops<KB, VB>::finalize_seq(st, s); }
+};
+template <int KB, int VB> struct DoLogical {
+    static int run(radsort_state* st, void* k, void* v, hipStream_t s)
+    {
+        return Ops<KB, VB>::logical(st, k, v, s);
+    }
+};
+template <int KB, int VB> struct DoOop {
+    static int run(void* k, void* v, const Geo& g, const Layout& L, uint8_t* ws, hipStream_t s)
+    {
+        return Ops<KB, VB>::oop_sort(k, v, g, L, ws, s);
+    }
+};
+
+int check_args(void* keys, void* payload, uint64_t n, int payload_bytes)
+{
+    if (n > 0 && !keys) return RADSORT_E_INVALID;
+    if (payload_bytes && n > 0 && !payload) return RADSORT_E_INVALID;
+    if (!payload_bytes && payload) return RADSORT_E_INVALID;
+    return RADSORT_OK;
+}
+
+int read_err(radsort_state* st, hipStream_t s, uint32_t* bits)
+{
+    uint32_t e = 0;
+    RS_HIP(hipMemcpyAsync(&e, st->err(), 4, hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    if (bits) *bits = e;
+    g_stats.error_bits = e;
+    return e ? RADSORT_E_TIMEOUT : RADSORT_OK;
+}
+
+}  // namespace
+
+// ---- C ABI ---------------------------------------------------------------------------
+
+extern "C" {
+
+int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_t n,
+                         int key_bytes, int payload_bytes, int digit_bits,
+                         const radsort_opts* opts)
+{
+    if (!out) return RADSORT_E_INVALID;
+    *out = nullptr;
+    int rc = check_args(keys, payload, n, payload_bytes);
+    if (rc) return rc;
+    Geo g;
+    rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts);
+    if (rc) return rc;
+    radsort_state* st = new (std::nothrow) radsort_state();
+    if (!st) return RADSORT_E_NOMEM;
+    st->g = g;
+    st->L = make_layout(g, false);
+    st->keys = keys;
+    st->vals = payload;
+    if (opts && opts->workspace) {
+        if (opts->workspace_bytes < st->L.total) {
+            delete st;
+            return RADSORT_E_NOMEM;
+        }
+        st->ws = (uint8_t*)opts->workspace;
+    } else {
+        hipError_t e = hipMalloc((void**)&st->ws, st->L.total);
+        if (e != hipSuccess) {
+            g_last_hip = e;
+            delete st;
+            return RADSORT_E_NOMEM;
+        }
+        st->own_ws = true;
+    }
+    *out = st;
+    return RADSORT_OK;
+}
+
+int radsort_state_setup(radsort_state* st, void* stream)
+{
+    if (!st) return RADSORT_E_INVALID;
+    int rc = dispatch<DoSetup>(st->g.kb, st->g.vb, st, (hipStream_t)stream);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    return RADSORT_OK;
+}
+
+int radsort_state_round(radsort_state* st, void* stream)
+{
+    if (!st || !st->is_setup || st->rounds_done >= st->g.nt) return RADSORT_E_INVALID;
+    int rc = dispatch<DoRound>(st->g.kb, st->g.vb, st, (hipStream_t)stream);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    return RADSORT_OK;
+}
+
+int radsort_state_finalize(radsort_state* st, void* stream)
+{
+    if (!st || !st->is_setup) return RADSORT_E_INVALID;
+    int rc = dispatch<DoFinalize>(st->g.kb, st->g.vb, st, (hipStream_t)stream);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    st->is_setup = false;
+    return RADSORT_OK;
+}
+
+int radsort_state_finalize_sequential(radsort_state* st, void* stream)
+{
+    if (!st || !st->is_setup) return RADSORT_E_INVALID;
+    int rc = dispatch<DoFinalizeSeq>(st->g.kb, st->g.vb, st, (hipStream_t)stream);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    st->is_setup = false;
+    return RADSORT_OK;
+}
+
+int radsort_state_read(radsort_state* st, uint32_t* pi, uint32_t* P_idx, uint32_t* P_len,
+                       uint32_t* f, void* stream)
+{
+    if (!st) return RADSORT_E_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    const Geo& g = st->g;
+    const uint32_t r = st->rounds_done;
+    if (pi) RS_HIP(hipMemcpyAsync(pi, st->pi(st->cur), 4ull * g.npi, hipMemcpyDeviceToHost, s));
+    if (P_idx)
+        RS_HIP(hipMemcpyAsync(P_idx, st->u32(st->L.Pidx) + r * g.sigma, 4ull * g.sigma,
+                              hipMemcpyDeviceToHost, s));
+    if (P_len)
+        RS_HIP(hipMemcpyAsync(P_len, st->u32(st->L.Plen) + r * g.sigma, 4ull * g.sigma,
+                              hipMemcpyDeviceToHost, s));
+    if (f) RS_HIP(hipMemcpyAsync(f, st->u32(st->L.f) + r, 4, hipMemcpyDeviceToHost, s));
+    return read_err(st, s, nullptr);
+}
+
+int radsort_state_logical(radsort_state* st, void* keys_out, void* payload_out, void* stream)
+{
+    if (!st || (st->g.n && !keys_out) || (st->g.vb && st->g.n && !payload_out))
+        return RADSORT_E_INVALID;
+    int rc = dispatch<DoLogical>(st->g.kb, st->g.vb, st, keys_out, payload_out,
+                                 (hipStream_t)stream);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    return RADSORT_OK;
+}
+
+int radsort_state_dims(const radsort_state* st, uint32_t* npi, uint32_t* sigma, uint32_t* nt)
+{
+    if (!st) return RADSORT_E_INVALID;
+    if (npi) *npi = st->g.npi;
+    if (sigma) *sigma = st->g.sigma;
+    if (nt) *nt = st->g.nt;
+    return RADSORT_OK;
+}
+
+int radsort_state_destroy(radsort_state* st)
+{
+    if (!st) return RADSORT_OK;
+    if (st->own_ws && st->ws) (void)hipFree(st->ws);
+    delete st;
+    return RADSORT_OK;
+}
+
+uint64_t radsort_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes, int digit_bits,
+                                 const radsort_opts* opts)
+{
+    Geo g;
+    if (make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts)) return 0;
+    return make_layout(g, false).total;
+}
+
+uint64_t radsort_oop_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes,
+                                     int digit_bits, const radsort_opts* opts)
+{
+    Geo g;
+    if (make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts)) return 0;
+    return make_layout(g, true).total;
+}
+
+int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes, int payload_bytes,
+                       int digit_bits, const radsort_opts* opts, void* stream)
+{
+    int rc = check_args(keys, payload, n, payload_bytes);
+    if (rc) return rc;
+    Geo g;
+    rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts);
+    if (rc) return rc;
+    if (n <= 1) return RADSORT_OK;
+    radsort_state* st = nullptr;
+    rc = radsort_state_create(&st, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rc = radsort_state_setup(st, s);
+    for (uint32_t r = 0; !rc && r < st->g.nt; r++) rc = radsort_state_round(st, s);
+    if (!rc) rc = radsort_state_finalize(st, s);
+    g_stats.workspace_bytes = st->L.total;
+    g_stats.input_bytes = n * (uint64_t)(key_bytes + payload_bytes);
+    g_stats.rounds = st->g.nt;
+    const bool check = opts && (opts->flags & RADSORT_F_CHECK);
+    if (!rc && (check || st->own_ws)) rc = read_err(st, s, nullptr);
+    radsort_state_destroy(st);  // a library-owned workspace is freed after read_err's wait
+    return rc;
+}
+
+int radsort_sort(void* keys, uint64_t n, int key_bytes, int digit_bits, void* stream)
+{
+    return radsort_sort_pairs(keys, nullptr, n, key_bytes, 0, digit_bits, nullptr, stream);
+}
+
+int radsort_oop_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
+                           int payload_bytes, int digit_bits, const radsort_opts* opts,
+                           void* stream)
+{
+    int rc = check_args(keys, payload, n, payload_bytes);
+    if (rc) return rc;
+    Geo g;
+    rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts);
+    if (rc) return rc;
+    if (n <= 1) return RADSORT_OK;
+    Layout L = make_layout(g, true);
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* ws = nullptr;
+    bool own = false;
+    if (opts && opts->workspace) {
+        if (opts->workspace_bytes < L.total) return RADSORT_E_NOMEM;
+        ws = (uint8_t*)opts->workspace;
+    } else {
+        hipError_t e = hipMalloc((void**)&ws, L.total);
+        if (e != hipSuccess) {
+            g_last_hip = e;
+            return RADSORT_E_NOMEM;
+        }
+        own = true;
+    }
+    rc = dispatch<DoOop>(g.kb, g.vb, keys, payload, g, L, ws, s);
+    if (!rc) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            g_last_hip = e;
+            rc = RADSORT_E_DEVICE;
+        }
+    }
+    g_stats.workspace_bytes = L.total;
+    g_stats.input_bytes = n * (uint64_t)(key_bytes + payload_bytes);
+    g_stats.rounds = g.nt;
+    const bool check = opts && (opts->flags & RADSORT_F_CHECK);
+    if (!rc && (check || own)) {
+        uint32_t e = 0;
+        hipError_t he = hipMemcpyAsync(&e, ws + L.ctr + 4ull * g.nt, 4, hipMemcpyDeviceToHost, s);
+        if (he == hipSuccess) he = hipStreamSynchronize(s);
+        if (he != hipSuccess) {
+            g_last_hip = he;
+            rc = RADSORT_E_DEVICE;
+        } else if (e) {
+            rc = RADSORT_E_TIMEOUT;
+        }
+        g_stats.error_bits = e;
+    }
+    if (own) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ws);
+    }
+    return rc;
+}
+
+int radsort_histograms(const void* keys, uint64_t n, int key_bytes, int digit_bits,
+                       uint32_t* counts, void* stream)
+{
+    if (!counts || (n && !keys)) return RADSORT_E_INVALID;
+    Geo g;
+    int rc = make_geo(g, n, key_bytes, 0, digit_bits, nullptr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rc = key_bytes == 4 ? launch_histograms<4>(keys, g, counts, s)
+                        : launch_histograms<8>(keys, g, counts, s);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    return RADSORT_OK;
+}
+
+int radsort_last_stats(radsort_stats* out)
+{
+    if (!out) return RADSORT_E_INVALID;
+    *out = g_stats;
+    return RADSORT_OK;
+}
+
+const char* radsort_strerror(int code)
+{
+    switch (code) {
+    case RADSORT_OK: return "ok";
+    case RADSORT_E_INVALID: return "invalid argument";
+    case RADSORT_E_NOMEM: return "out of memory or workspace too small";
+    case RADSORT_E_DEVICE: return hipGetErrorString(g_last_hip);
+    case RADSORT_E_UNSUPPORTED: return "unsupported size or digit width";
+    case RADSORT_E_TIMEOUT: return "a device-side wait gave up (protocol error)";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/radsort.h declares, sizes its workspace, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2607_05302_amd as radsort
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "radsort.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(radsort_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(radsort.ABI)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = radsort.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_formula_and_one_percent_budget():
+    # n = 2^28 uint32 keys + uint32 payload, b = 1024, 8-bit digits
+    n = 1 << 28
+    ws = radsort.workspace_bytes(n, 4, 4, 8, 1024)
+    sigma, b = 256, 1024
+    t_bytes = 2 * sigma * b * 8
+    npi = n // b + 2 * sigma
+    assert ws >= t_bytes + 2 * 4 * npi
+    assert ws <= 0.01 * n * 8, ws / (n * 8)
+    # the out-of-place baseline needs a second array
+    assert radsort.oop_workspace_bytes(n, 4, 4, 8, 1024) >= n * 8
+
+
+def test_workspace_is_order_sqrt_n():
+    ratios = []
+    for lg in range(16, 31, 2):
+        n = 1 << lg
+        b = max(64, 1 << ((lg + 1) // 2))
+        ratios.append(radsort.workspace_bytes(n, 4, 4, 8, b) / (n ** 0.5))
+    assert max(ratios) / min(ratios) < 8
+
+
+@pytest.mark.parametrize("args,code", [
+    ((1000, 3, 0, 8), radsort.E_INVALID),      # key width
+    ((1000, 4, 2, 8), radsort.E_INVALID),      # payload width
+    ((1000, 4, 0, 0), radsort.E_INVALID),      # digit width
+    ((1000, 4, 0, 12), radsort.E_UNSUPPORTED),
+    ((1 << 32, 4, 0, 8), radsort.E_UNSUPPORTED),
+])
+def test_argument_errors(args, code):
+    lib = radsort.load()
+    n, kb, vb, bits = args
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation comes first
+    rc = lib.radsort_sort_pairs(fake, fake if vb else None, n, kb, vb, bits, None, None)
+    assert rc == code
+    assert radsort.workspace_bytes(n, kb, vb, bits) == 0
+
+
+@pytest.mark.parametrize("b", [32, 100, 1 << 17])
+def test_block_size_validation(b):
+    lib = radsort.load()
+    o = radsort.Opts()
+    o.block_elems = b
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.radsort_sort_pairs(fake, None, 1000, 4, 0, 8, ctypes.byref(o), None)
+    assert rc == radsort.E_INVALID
+    assert radsort.workspace_bytes(1000, 4, 0, 8, b) == 0
+
+
+def test_workspace_too_small_is_rejected():
+    lib = radsort.load()
+    o = radsort.Opts()
+    o.block_elems = 1024
+    o.workspace = 0x2000
+    o.workspace_bytes = 16
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.radsort_sort_pairs(fake, None, 100000, 4, 0, 8, ctypes.byref(o), None) == \
+        radsort.E_NOMEM
+    assert lib.radsort_oop_sort_pairs(fake, None, 100000, 4, 0, 8, ctypes.byref(o), None) == \
+        radsort.E_NOMEM
+
+
+def test_null_pointers_rejected():
+    lib = radsort.load()
+    assert lib.radsort_sort_pairs(None, None, 10, 4, 0, 8, None, None) == radsort.E_INVALID
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.radsort_sort_pairs(fake, None, 10, 4, 4, 8, None, None) == radsort.E_INVALID
+    assert lib.radsort_sort_pairs(fake, fake, 10, 4, 0, 8, None, None) == radsort.E_INVALID
+    assert lib.radsort_state_create(None, fake, None, 10, 4, 0, 8, None) == radsort.E_INVALID
+    assert lib.radsort_histograms(fake, 10, 4, 8, None, None) == radsort.E_INVALID
+
+
+def test_trivial_sizes_are_no_ops():
+    lib = radsort.load()
+    # n <= 1 returns before anything is enqueued, so no device is needed
+    assert lib.radsort_sort_pairs(None, None, 0, 4, 0, 8, None, None) == radsort.OK
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.radsort_sort_pairs(fake, None, 1, 8, 0, 8, None, None) == radsort.OK
+    assert lib.radsort_oop_sort_pairs(fake, fake, 1, 8, 8, 8, None, None) == radsort.OK
+
+
+def test_strerror_texts():
+    for code in (radsort.OK, radsort.E_INVALID, radsort.E_NOMEM, radsort.E_UNSUPPORTED,
+                 radsort.E_TIMEOUT):
+        assert radsort.strerror(code)
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    with pytest.raises(RuntimeError):
+        radsort.load(str(tmp_path / "missing.so"))

@@ -1,0 +1,228 @@
+"""GPU parity: the HIP path against the sequential oracle, through the C ABI.
+
+Every comparison is exact.  Radsort's integer state is deterministic: the GPU
+draws blocks from the pool in the same order as the sequential algorithm, so
+pi, P and f after setup and after every round must equal the oracle's bit for
+bit, and so must the permuted representation read in logical order and the
+final arrays.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+import paper_2607_05302_amd as radsort  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+NP = {4: np.uint32, 8: np.uint64}
+TV = {4: torch.int32, 8: torch.int64}
+
+
+def to_dev(a):
+    a = np.ascontiguousarray(a)
+    view = {4: np.int32, 8: np.int64}[a.dtype.itemsize]
+    return torch.from_numpy(a.view(view)).to(DEV)
+
+
+def from_dev(t, width):
+    return t.cpu().numpy().view(NP[width])
+
+
+def inputs(dist, n, kb, vb, seed=1):
+    keys = workloads.make(dist, seed * 1000003 + n, n, kb)
+    vals = np.arange(n, dtype=NP[vb]) if vb else None
+    return keys, vals
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------- a0: histograms
+
+@pytest.mark.parametrize("kb,bits", [(4, 8), (4, 4), (4, 11), (8, 8), (8, 11), (4, 1)])
+@pytest.mark.parametrize("n", [0, 1, 1000, (1 << 20) + 5])
+def test_histograms(kb, bits, n):
+    say(f"histograms kb={kb} bits={bits} n={n}")
+    keys, _ = inputs("uniform", n, kb, 0)
+    sigma, nt = oracle.digit_params(kb, bits)
+    h = radsort.histograms(to_dev(keys), bits)
+    torch.cuda.synchronize()
+    got = h.cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert np.array_equal(got, oracle.histograms(keys, sigma, nt))
+
+
+# ---------------------------------------------------------------- a1-a7: rounds
+
+ROUND_CASES = [
+    # (dist, n, key bytes, payload bytes, digit bits, b)
+    ("uniform", 5000, 4, 4, 8, 64),
+    ("uniform", (1 << 16) + 777, 4, 4, 8, 1024),
+    ("uniform", 1 << 20, 4, 4, 8, 1024),
+    ("uniform", 300000, 4, 0, 8, 256),
+    ("uniform", 100000, 8, 4, 8, 512),
+    ("uniform", 70000, 8, 8, 11, 1024),
+    ("uniform", 50000, 4, 8, 4, 128),
+    ("equal", 200000, 4, 4, 8, 1024),
+    ("sorted", 200000, 4, 4, 8, 1024),
+    ("zipf", 300000, 8, 4, 8, 1024),
+    ("low20", 200000, 8, 0, 8, 1024),
+    ("few", 123457, 4, 4, 8, 64),
+    ("uniform", 1000, 4, 4, 8, 4096),       # fewer elements than one block
+    ("uniform", 70000, 4, 4, 8, 16384),     # blocks larger than a tile
+    ("uniform", 3, 4, 4, 8, 64),
+]
+
+
+@pytest.mark.parametrize("case", ROUND_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_rounds_match_oracle(case):
+    dist, n, kb, vb, bits, b = case
+    say(f"rounds {case}")
+    keys, vals = inputs(dist, n, kb, vb)
+    sigma, nt = oracle.digit_params(kb, bits)
+    dk = to_dev(keys)
+    dv = to_dev(vals) if vb else None
+    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b)
+    R = oracle.Radsort(keys, vals, sigma, nt, b)
+    st.setup()
+    R.setup()
+    for r in range(-1, nt):
+        if r >= 0:
+            st.round()
+            R.round(nt - 1 - r)
+        pi, pidx, plen, f = st.read()
+        assert f == R.f, (r, f, R.f)
+        assert np.array_equal(pi.astype(np.uint64), R.pi()), f"pi differs after round {r}"
+        oidx, olen = R.P()
+        assert np.array_equal(pidx.astype(np.uint64), oidx), f"P idx differs after round {r}"
+        assert np.array_equal(plen.astype(np.uint64), olen), f"P len differs after round {r}"
+        lk, lv = st.logical()
+        ok, ov, cnt = R.logical()
+        assert cnt == n
+        assert np.array_equal(from_dev(lk, kb).astype(np.uint64), ok), f"logical keys, round {r}"
+        if vb:
+            assert np.array_equal(from_dev(lv, vb).astype(np.uint64), ov), f"logical payload {r}"
+    st.close()
+
+
+# ---------------------------------------------------------------- a8: finalize
+
+@pytest.mark.parametrize("case", ROUND_CASES, ids=lambda c: "-".join(map(str, c)))
+@pytest.mark.parametrize("mode", ["parallel", "sequential"])
+def test_finalize_matches_oracle(case, mode):
+    dist, n, kb, vb, bits, b = case
+    if mode == "sequential" and n > 300000:
+        pytest.skip("the one-workgroup finalize is slow at this size")
+    say(f"finalize {mode} {case}")
+    keys, vals = inputs(dist, n, kb, vb, seed=2)
+    sigma, nt = oracle.digit_params(kb, bits)
+    dk = to_dev(keys)
+    dv = to_dev(vals) if vb else None
+    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b)
+    st.setup()
+    for _ in range(nt):
+        st.round()
+    (st.finalize if mode == "parallel" else st.finalize_sequential)()
+    st.read()  # waits and reports device-side errors
+    ok, ov = oracle.radsort(keys, vals, sigma, nt, b)
+    assert np.array_equal(from_dev(dk, kb).astype(np.uint64), ok)
+    if vb:
+        assert np.array_equal(from_dev(dv, vb).astype(np.uint64), ov)
+    st.close()
+
+
+# ---------------------------------------------------------------- end to end
+
+E2E = [
+    ("uniform", 1 << 20, 4, 4, 8, 1024),      # the small configuration
+    ("uniform", (1 << 20) + 12345, 4, 4, 8, 1024),
+    ("uniform", 1 << 22, 4, 4, 8, 1024),
+    ("uniform", 1 << 21, 8, 4, 8, 1024),
+    ("uniform", 1 << 20, 4, 0, 8, 2048),
+    ("uniform", 1 << 20, 8, 8, 4, 1024),
+    ("uniform", 1 << 20, 4, 4, 11, 1024),
+    ("zipf", 1 << 21, 8, 4, 8, 1024),
+    ("equal", 1 << 21, 8, 4, 8, 1024),
+    ("sorted", 1 << 21, 8, 4, 8, 1024),
+    ("low20", 1 << 21, 8, 4, 8, 1024),
+    ("reverse", 1 << 20, 4, 4, 8, 1024),
+    ("uniform", 2, 4, 4, 8, 1024),
+    ("uniform", 65, 4, 4, 8, 64),
+]
+
+
+@pytest.mark.parametrize("case", E2E, ids=lambda c: "-".join(map(str, c)))
+def test_sort_pairs_matches_oracle(case):
+    dist, n, kb, vb, bits, b = case
+    say(f"sort_pairs {case}")
+    keys, vals = inputs(dist, n, kb, vb, seed=3)
+    sigma, nt = oracle.digit_params(kb, bits)
+    dk = to_dev(keys)
+    dv = to_dev(vals) if vb else None
+    radsort.sort_(dk, dv, digit_bits=bits, block_elems=b, check=True)
+    ok, ov = oracle.radsort(keys, vals, sigma, nt, b)
+    assert np.array_equal(from_dev(dk, kb).astype(np.uint64), ok)
+    if vb:
+        assert np.array_equal(from_dev(dv, vb).astype(np.uint64), ov)
+
+
+@pytest.mark.parametrize("case", E2E[:8], ids=lambda c: "-".join(map(str, c)))
+def test_oop_matches_oracle(case):
+    dist, n, kb, vb, bits, b = case
+    say(f"oop {case}")
+    keys, vals = inputs(dist, n, kb, vb, seed=4)
+    sigma, nt = oracle.digit_params(kb, bits)
+    dk = to_dev(keys)
+    dv = to_dev(vals) if vb else None
+    radsort.oop_sort_(dk, dv, digit_bits=bits, block_elems=b, check=True)
+    ok, ov = oracle.oop_lsd(keys, vals, sigma, nt)
+    assert np.array_equal(from_dev(dk, kb).astype(np.uint64), ok)
+    if vb:
+        assert np.array_equal(from_dev(dv, vb).astype(np.uint64), ov)
+
+
+def test_caller_workspace_and_stats():
+    n = 1 << 20
+    keys, vals = inputs("uniform", n, 4, 4, seed=5)
+    need = radsort.workspace_bytes(n, 4, 4, 8, 1024)
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    dk, dv = to_dev(keys), to_dev(vals)
+    radsort.sort_(dk, dv, workspace=ws, check=True)
+    ok, ov = oracle.radsort(keys, vals, 256, 4, 1024)
+    assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
+    assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov)
+    s = radsort.last_stats()
+    assert s["workspace_bytes"] == need and s["error_bits"] == 0
+
+
+def test_repeated_calls_on_one_stream():
+    """Back-to-back sorts reuse nothing stale: the ring, counters and pi are reset."""
+    n = 1 << 18
+    s = torch.cuda.Stream()
+    ws = torch.empty(radsort.workspace_bytes(n, 4, 4, 8), dtype=torch.uint8, device=DEV)
+    for seed in range(3):
+        keys, vals = inputs("uniform", n, 4, 4, seed=10 + seed)
+        dk, dv = to_dev(keys), to_dev(vals)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            radsort.sort_(dk, dv, workspace=ws, stream=s, check=True)
+        s.synchronize()
+        ok, ov = oracle.radsort(keys, vals, 256, 4, 1024)
+        assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
+        assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov)
+
+
+def test_ring_wraps_within_a_round():
+    """2^24 pairs: more tiles per round than look-back ring slots."""
+    n = 1 << 24
+    say(f"ring wrap n={n}")
+    keys, vals = inputs("uniform", n, 4, 4, seed=6)
+    dk, dv = to_dev(keys), to_dev(vals)
+    radsort.sort_(dk, dv, check=True)
+    ok, ov = oracle.radsort(keys, vals, 256, 4, 1024)
+    assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
+    assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov)
