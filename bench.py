@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Radsort on one MI355X against the out-of-place LSD baseline of Alg. 1.
+
+Workload: n = 2^28 uint32 keys, uniform over [0, 2^32) (splitmix64, seed
+0x5EED0002), uint32 payload = original index, 8-bit digits (sigma = 256, n_t = 4),
+block size b = 1024.  One step is one complete Radsort of that array on the GPU:
+digit histograms, setup, four sort rounds with their fixups, and finalize.  The
+input is restored from a pristine device copy before every step; the restore
+lies outside the HIP events that time the step.
+
+Printed: one JSON line with keys/s (value), the per-round roofline of the
+sort-round kernel (algorithmic bytes 2 n (s_k + s_v) per launch over its event
+time), peak extra device bytes of Radsort and of the baseline, the baseline's
+throughput on the same input, and the CPU oracle timed on a sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "keys/s & HBM GB/s, uint32 n=2^28, vs out-of-place LSD; peak extra bytes"
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_round_traffic.json")
+KERNEL_SOURCES = ["paper_2607_05302_amd/csrc/kernel_round.hpp",
+                  "paper_2607_05302_amd/csrc/common.hpp"]
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(n, elem_bytes):
+    """HBM bytes per sort-round launch from the committed counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha() or t.get("n") != n or t.get("elem_bytes") != elem_bytes:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(keys_np, target_s):
+    """The sequential C oracle on a prefix of the same input (1 host thread)."""
+    import numpy as np
+
+    import oracle
+
+    oracle.load()
+    m = 1 << 20
+    t = time.perf_counter()
+    oracle.radsort(keys_np[:m], np.arange(m, dtype=np.uint32), 256, 4, 1024)
+    per_key = (time.perf_counter() - t) / m
+    m = int(min(len(keys_np), max(1 << 20, target_s / per_key)))
+    m = 1 << (m.bit_length() - 1)  # a power of two
+    vals = np.arange(m, dtype=np.uint32)
+    t = time.perf_counter()
+    oracle.radsort(keys_np[:m], vals, 256, 4, 1024)
+    dt = time.perf_counter() - t
+    return {"value": m / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m} of the {len(keys_np)} keys (2^{m.bit_length() - 1}), "
+                      f"uint32 keys + uint32 index payload, b=1024, 8-bit digits, sequential "
+                      f"C oracle (Alg. 2-7), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--block", type=int, default=1024)
+    ap.add_argument("--no-oop", action="store_true", help="skip the out-of-place baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (scales HBM counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); the sort runs on a single MI355X.", flush=True)
+        sys.exit(1)
+
+    import numpy as np
+    import torch
+
+    import paper_2607_05302_amd as radsort
+    import workloads
+
+    n = 1 << args.log2n
+    b, bits, kb, vb = args.block, 8, 4, 4
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"bench: generating n=2^{args.log2n} uniform uint32 keys")
+    keys_np = workloads.uniform(workloads.SEED_LARGE, n, 4)
+    keys0 = torch.from_numpy(keys_np.view(np.int32)).to(dev)
+    vals0 = torch.arange(n, dtype=torch.int32, device=dev)
+    keys = torch.empty_like(keys0)
+    vals = torch.empty_like(vals0)
+    ws_bytes = radsort.workspace_bytes(n, kb, vb, bits, b)
+    oop_bytes = radsort.oop_workspace_bytes(n, kb, vb, bits, b)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def run(fn, wsbuf, steps, warmup, label):
+        for _ in range(warmup):
+            keys.copy_(keys0)
+            vals.copy_(vals0)
+            fn(keys, vals, digit_bits=bits, block_elems=b, workspace=wsbuf, check=True)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        times, stats = [], []
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for _ in range(steps):
+            keys.copy_(keys0)
+            vals.copy_(vals0)
+            ev0.record(stream)
+            fn(keys, vals, digit_bits=bits, block_elems=b, workspace=wsbuf, timing=True)
+            ev1.record(stream)
+            st = radsort.last_stats()  # waits for the sort's own last event
+            ev1.synchronize()
+            times.append(ev0.elapsed_time(ev1))
+            stats.append(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        log(f"bench: {label}: mean {np.mean(times):.3f} ms, min {np.min(times):.3f} ms")
+        return times, stats, wall
+
+    log("bench: Radsort")
+    times, stats, wall = run(radsort.sort_, ws, args.steps, args.warmup, "radsort")
+    # check the last result: sorted, stable, and a permutation carrying its keys
+    k = keys.to(torch.int64) & 0xFFFFFFFF
+    v = vals.to(torch.int64)
+    ok = bool((k[1:] >= k[:-1]).all())
+    eq = k[1:] == k[:-1]
+    ok &= bool((v[1:][eq] > v[:-1][eq]).all())
+    ok &= bool(((keys0.to(torch.int64) & 0xFFFFFFFF)[v] == k).all())
+    ok &= bool((torch.bincount(v, minlength=n) == 1).all())
+    del k, v, eq
+    if not ok:
+        log("bench: Radsort output failed the sortedness/stability/permutation check")
+
+    oop = None
+    if not args.no_oop:
+        log("bench: out-of-place baseline")
+        del ws
+        torch.cuda.empty_cache()
+        ows = torch.empty(oop_bytes, dtype=torch.uint8, device=dev)
+        otimes, ostats, _ = run(radsort.oop_sort_, ows, args.steps, args.warmup, "oop")
+        del ows
+        torch.cuda.empty_cache()
+        oop = {
+            "value": n / (np.mean(otimes) / 1e3), "unit": "keys/s",
+            "ms_per_step": float(np.mean(otimes)), "min_ms": float(np.min(otimes)),
+            "round_ms_mean": float(np.mean([np.mean(s["round_ms"]) for s in ostats])),
+            "peak_extra_bytes": oop_bytes,
+            "peak_extra_frac_of_input": oop_bytes / (n * (kb + vb)),
+        }
+
+    if args.copy_calibration:
+        # a plain copy of known size: the HBM counters of this kernel give the scale
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy calibration: 1 GiB read + 1 GiB write per copy, 3 copies")
+        del src, dst
+
+    mean_ms = float(np.mean(times))
+    round_ms = [float(np.mean([s["round_ms"][r] for s in stats])) for r in range(4)]
+    per_round = float(np.mean(round_ms))
+    alg_bytes = 2 * n * (kb + vb)  # n reads + n writes of (key, payload) per round
+    achieved = alg_bytes / (per_round / 1e3) / 1e9
+    traffic = measured_traffic(n, kb + vb)
+    out = {
+        "metric": METRIC,
+        "value": n / (mean_ms / 1e3),
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mean_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"radsort n=2^{args.log2n} uint32 keys uniform (splitmix64 seed "
+                        f"0x5EED0002) + uint32 index payload, 8-bit digits, b={b}",
+            "n": n, "key_bytes": kb, "payload_bytes": vb, "digit_bits": bits,
+            "block_elems": b,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_round (one sort round, Alg. 5)",
+            "alg_bytes_per_launch": alg_bytes, "launch_ms": per_round,
+        },
+        "hbm_gbps_whole_sort": 4 * alg_bytes / (mean_ms / 1e3) / 1e9,
+        "phases_ms": {
+            "setup": float(np.mean([s["setup_ms"] for s in stats])),
+            "rounds": round_ms,
+            "fixup_total": float(np.mean([s["fixup_ms"] for s in stats])),
+            "finalize": float(np.mean([s["finalize_ms"] for s in stats])),
+        },
+        "min_ms": float(np.min(times)),
+        "runs_ms": [round(t, 4) for t in times],
+        "wall_ms_per_step_incl_restore": wall / args.steps * 1e3,
+        "peak_extra_bytes": ws_bytes,
+        "peak_extra_frac_of_input": ws_bytes / (n * (kb + vb)),
+        "oop": oop,
+        "verified": ok,
+    }
+    if oop:
+        out["speed_vs_oop"] = oop["ms_per_step"] / mean_ms
+        out["extra_bytes_vs_oop"] = ws_bytes / oop_bytes
+    if not args.no_cpu_baseline:
+        log("bench: CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -44,6 +44,8 @@ extern "C" {
 
 /* flags of radsort_opts */
 #define RADSORT_F_CHECK 1u          /* wait for the stream and report device-side errors */
+#define RADSORT_F_TIMING 2u         /* record HIP events around each phase on the stream;
+                                       radsort_last_stats() waits for them and reports */
 
 typedef struct radsort_opts {
     uint32_t block_elems;     /* b: block size in elements, a power of two in [64, 65536];
@@ -54,11 +56,20 @@ typedef struct radsort_opts {
     uint32_t flags;           /* RADSORT_F_* */
 } radsort_opts;
 
+#define RADSORT_MAX_ROUNDS 64
+
 typedef struct radsort_stats {
     uint64_t workspace_bytes;   /* extra device bytes of the last sort (peak extra memory) */
     uint64_t input_bytes;       /* n * (key_bytes + payload_bytes) of the last sort */
     uint32_t rounds;            /* digit rounds run */
     uint32_t error_bits;        /* device error word of the last checked call */
+    /* with RADSORT_F_TIMING: milliseconds between HIP events on the call's stream */
+    uint32_t timed;             /* 1 when the fields below are valid */
+    float setup_ms;             /* histograms, plan and setup (Alg. 4) */
+    float round_ms[RADSORT_MAX_ROUNDS]; /* the sort-round kernel of each round (Alg. 5) */
+    float fixup_ms;             /* all fixup kernels (Alg. 6) and counter resets */
+    float finalize_ms;          /* finalize (Alg. 7); for the baseline: a final copy-back */
+    float total_ms;             /* first event to last event */
 } radsort_stats;
 
 /*
@@ -113,7 +124,8 @@ uint64_t radsort_oop_workspace_bytes(uint64_t n, int key_bytes, int payload_byte
 int radsort_histograms(const void* keys, uint64_t n, int key_bytes, int digit_bits,
                        uint32_t* counts, void* stream);
 
-/* Statistics of the last completed sort call of this process. */
+/* Statistics of the last sort call of this process.  If that call asked for
+ * RADSORT_F_TIMING, this waits for its last event first. */
 int radsort_last_stats(radsort_stats* out);
 
 /* Text for a return code (and, after RADSORT_E_DEVICE, the HIP error). */

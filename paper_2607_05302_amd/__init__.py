@@ -21,7 +21,8 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libradsort.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_TIMEOUT = 0, -1, -2, -3, -4, -5
-F_CHECK = 1
+F_CHECK, F_TIMING = 1, 2
+MAX_ROUNDS = 64
 
 # every function declared in include/radsort.h
 ABI = [
@@ -47,7 +48,10 @@ class Opts(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("workspace_bytes", ctypes.c_uint64), ("input_bytes", ctypes.c_uint64),
-                ("rounds", ctypes.c_uint32), ("error_bits", ctypes.c_uint32)]
+                ("rounds", ctypes.c_uint32), ("error_bits", ctypes.c_uint32),
+                ("timed", ctypes.c_uint32), ("setup_ms", ctypes.c_float),
+                ("round_ms", ctypes.c_float * MAX_ROUNDS), ("fixup_ms", ctypes.c_float),
+                ("finalize_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
 
 
 _lib = None
@@ -152,10 +156,10 @@ def oop_workspace_bytes(n, key_bytes=4, payload_bytes=0, digit_bits=8, block_ele
 
 
 def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, workspace=None,
-          check=False):
+          check=False, timing=False):
     """Radsort in place on the current stream (radsort_sort_pairs)."""
     kb, vb = _validate(keys, payload)
-    o = _opts(block_elems, workspace, F_CHECK if check else 0)
+    o = _opts(block_elems, workspace, (F_CHECK if check else 0) | (F_TIMING if timing else 0))
     with _device(keys):
         rc = load().radsort_sort_pairs(
             ctypes.c_void_p(keys.data_ptr()),
@@ -166,10 +170,10 @@ def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, works
 
 
 def oop_sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, workspace=None,
-              check=False):
+              check=False, timing=False):
     """The out-of-place LSD baseline of Alg. 1, in place from the caller's view."""
     kb, vb = _validate(keys, payload)
-    o = _opts(block_elems, workspace, F_CHECK if check else 0)
+    o = _opts(block_elems, workspace, (F_CHECK if check else 0) | (F_TIMING if timing else 0))
     with _device(keys):
         rc = load().radsort_oop_sort_pairs(
             ctypes.c_void_p(keys.data_ptr()),
@@ -195,10 +199,15 @@ def histograms(keys, digit_bits=8, stream=None):
 
 
 def last_stats() -> dict:
+    """Stats of the last sort; with timing=True it waits for that sort's events."""
     s = Stats()
     _check(load().radsort_last_stats(ctypes.byref(s)))
-    return {"workspace_bytes": s.workspace_bytes, "input_bytes": s.input_bytes,
-            "rounds": s.rounds, "error_bits": s.error_bits}
+    out = {"workspace_bytes": s.workspace_bytes, "input_bytes": s.input_bytes,
+           "rounds": s.rounds, "error_bits": s.error_bits, "timed": bool(s.timed)}
+    if s.timed:
+        out.update(setup_ms=s.setup_ms, round_ms=[s.round_ms[i] for i in range(s.rounds)],
+                   fixup_ms=s.fixup_ms, finalize_ms=s.finalize_ms, total_ms=s.total_ms)
+    return out
 
 
 class _device:

@@ -139,6 +139,70 @@ Layout make_layout(const Geo& g, bool oop)
     return L;
 }
 
+// HIP events recorded on the call's stream around each phase (RADSORT_F_TIMING).
+enum Mark { kStart, kSetupEnd, kRoundBegin, kRoundEnd, kFixupEnd, kFinBegin, kFinEnd };
+
+struct Timer {
+    static constexpr int kMax = 8 + 3 * RADSORT_MAX_ROUNDS;
+    hipEvent_t ev[kMax];
+    int tag[kMax], round[kMax];
+    int count = 0;
+    bool created = false, active = false, pending = false;
+
+    void begin()
+    {
+        if (!created) {
+            for (int i = 0; i < kMax; i++) (void)hipEventCreate(&ev[i]);
+            created = true;
+        }
+        count = 0;
+        active = true;
+        pending = false;
+    }
+    void mark(Mark m, int r, hipStream_t s)
+    {
+        if (!active || count >= kMax) return;
+        tag[count] = m;
+        round[count] = r;
+        (void)hipEventRecord(ev[count], s);
+        count++;
+    }
+    void end()
+    {
+        if (active) pending = count > 0;
+        active = false;
+    }
+    // waits for the last event and fills the timing fields of st
+    void report(radsort_stats& st)
+    {
+        if (!pending) return;
+        pending = false;
+        if (hipEventSynchronize(ev[count - 1]) != hipSuccess) return;
+        auto ms = [&](int a, int b) {
+            float t = 0;
+            (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+            return t;
+        };
+        st.timed = 1;
+        st.setup_ms = st.fixup_ms = st.finalize_ms = 0;
+        for (int r = 0; r < RADSORT_MAX_ROUNDS; r++) st.round_ms[r] = 0;
+        st.total_ms = ms(0, count - 1);
+        for (int i = 1; i < count; i++) {
+            const float d = ms(i - 1, i);
+            switch (tag[i]) {
+            case kSetupEnd: st.setup_ms += d; break;
+            case kRoundEnd: st.round_ms[round[i] % RADSORT_MAX_ROUNDS] += d; break;
+            case kRoundBegin:
+            case kFixupEnd: st.fixup_ms += d; break;
+            case kFinEnd: st.finalize_ms += d; break;
+            default: st.setup_ms += d; break;  // gaps before a finalize
+            }
+        }
+    }
+};
+
+Timer g_timer;
+
 void launch_fill(uint32_t* p, uint64_t count, uint32_t v, hipStream_t s)
 {
     if (!count) return;
@@ -216,6 +280,7 @@ template <int KB, int VB> struct Ops {
     static int setup(radsort_state* st, hipStream_t s)
     {
         const Geo& g = st->g;
+        g_timer.mark(kStart, 0, s);
         launch_histograms<KB>(st->keys, g, st->u32(st->L.hist), s);
         launch_plan(g, st->u32(st->L.hist), st->plan(), s);
         launch_fill(st->u32(st->L.ctr), g.nt + 8, 0, s);
@@ -225,6 +290,7 @@ template <int KB, int VB> struct Ops {
         hipLaunchKernelGGL((k_setup<KB, VB>), dim3(grid), dim3(256), 0, s, (K*)st->keys,
                            (V*)st->vals, (K*)(st->ws + st->L.Tk), (V*)(st->ws + st->L.Tv), g.n,
                            g.log2b, g.sigma, g.npi, st->pi(0), st->pi(1));
+        g_timer.mark(kSetupEnd, 0, s);
         st->cur = 0;
         st->rounds_done = 0;
         st->seq = 0;
@@ -258,10 +324,13 @@ template <int KB, int VB> struct Ops {
         a.npi = g.npi;
         a.ring_w = g.ring_w;
         launch_fill(a.tile_ctr, 1, 0, s);
+        g_timer.mark(kRoundBegin, r, s);
         launch_round_t<KB, VB, false>(g, a, s);
+        g_timer.mark(kRoundEnd, r, s);
         uint32_t grid = (uint32_t)std::min<uint64_t>((g.npi + 255) / 256, 4096);
         hipLaunchKernelGGL(k_fixup, dim3(grid), dim3(256), 0, s, st->pi(st->cur),
                            st->pi(st->cur ^ 1), a.S, st->u32(st->L.f) + r + 1, g.sigma, g.npi);
+        g_timer.mark(kFixupEnd, r, s);
         st->cur ^= 1;
         st->rounds_done++;
         st->seq += g.tiles;
@@ -300,7 +369,10 @@ template <int KB, int VB> struct Ops {
         a.err = st->err();
         a.scratch = st->ws + st->L.fin;
         a.spare_pi = st->pi(st->cur ^ 1);
-        return finalize_parallel<KB, VB>(a, s);
+        g_timer.mark(kFinBegin, 0, s);
+        int rc = finalize_parallel<KB, VB>(a, s);
+        g_timer.mark(kFinEnd, 0, s);
+        return rc;
     }
 
     static int logical(radsort_state* st, void* ok, void* ov, hipStream_t s)
@@ -324,11 +396,13 @@ template <int KB, int VB> struct Ops {
         uint32_t* hist = (uint32_t*)(ws + L.hist);
         PlanPtrs p{(uint32_t*)(ws + L.S), (uint32_t*)(ws + L.Pidx), (uint32_t*)(ws + L.Plen),
                    (uint32_t*)(ws + L.f), (uint32_t*)(ws + L.est)};
+        g_timer.mark(kStart, 0, s);
         launch_histograms<KB>(keys, g, hist, s);
         launch_plan(g, hist, p, s);
         uint32_t* ctr = (uint32_t*)(ws + L.ctr);
         launch_fill(ctr, g.nt + 8, 0, s);
         launch_fill((uint32_t*)(ws + L.ring), L.ring_bytes / 4, 0, s);
+        g_timer.mark(kSetupEnd, 0, s);
         K* bk[2] = {(K*)keys, (K*)(ws + L.alt_k)};
         V* bv[2] = {(V*)vals, (V*)(ws + L.alt_v)};
         const uint32_t tiles = (uint32_t)((g.n + g.E - 1) / g.E);
@@ -349,12 +423,16 @@ template <int KB, int VB> struct Ops {
             a.bits = g.bits;
             a.log2b = g.log2b;
             a.ring_w = g.ring_w;
+            g_timer.mark(kRoundBegin, r, s);
             launch_round_t<KB, VB, true>(g, a, s);
+            g_timer.mark(kRoundEnd, r, s);
         }
+        g_timer.mark(kFinBegin, 0, s);
         if (g.nt & 1) {  // the result is in the workspace buffer: copy it back
             RS_HIP(hipMemcpyAsync(keys, bk[1], g.n * KB, hipMemcpyDeviceToDevice, s));
             if (VB) RS_HIP(hipMemcpyAsync(vals, bv[1], g.n * VB, hipMemcpyDeviceToDevice, s));
         }
+        g_timer.mark(kFinEnd, 0, s);
         return RADSORT_OK;
     }
 };
@@ -569,9 +647,13 @@ int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes, int
     rc = radsort_state_create(&st, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
+    const bool timing = opts && (opts->flags & RADSORT_F_TIMING);
+    if (timing) g_timer.begin();
     rc = radsort_state_setup(st, s);
     for (uint32_t r = 0; !rc && r < st->g.nt; r++) rc = radsort_state_round(st, s);
     if (!rc) rc = radsort_state_finalize(st, s);
+    g_timer.end();
+    g_stats.timed = 0;
     g_stats.workspace_bytes = st->L.total;
     g_stats.input_bytes = n * (uint64_t)(key_bytes + payload_bytes);
     g_stats.rounds = st->g.nt;
@@ -611,7 +693,11 @@ int radsort_oop_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
         }
         own = true;
     }
+    const bool timing = opts && (opts->flags & RADSORT_F_TIMING);
+    if (timing) g_timer.begin();
     rc = dispatch<DoOop>(g.kb, g.vb, keys, payload, g, L, ws, s);
+    g_timer.end();
+    g_stats.timed = 0;
     if (!rc) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) {
@@ -660,6 +746,7 @@ int radsort_histograms(const void* keys, uint64_t n, int key_bytes, int digit_bi
 int radsort_last_stats(radsort_stats* out)
 {
     if (!out) return RADSORT_E_INVALID;
+    g_timer.report(g_stats);
     *out = g_stats;
     return RADSORT_OK;
 }
