@@ -73,6 +73,17 @@ __device__ __forceinline__ void raise_error(uint32_t* err, uint32_t bit)
 
 __device__ __forceinline__ void spin_pause() { __builtin_amdgcn_s_sleep(1); }
 
+// True when a bounded wait must give up: after kSpinLimit polls, or when another
+// wait already gave up (the error word is polled every 256th time only).
+__device__ __forceinline__ bool spin_give_up(uint32_t spins, uint32_t* err)
+{
+    if (spins > kSpinLimit) {
+        raise_error(err, kErrSpin);
+        return true;
+    }
+    return (spins & 255u) == 0 && ld_agent(err) != 0;
+}
+
 // --- blocks (Eq. 1): physical index j < 2 sigma lives in T, the rest overlays A ---
 
 template <typename X>

@@ -54,11 +54,11 @@ struct TileArgs {
     const uint32_t* S;       // first logical block of each output bucket
     const uint32_t* est;     // out-of-place only: element start of each bucket
     uint64_t n;              // out-of-place only
-    uint64_t* ring;          // look-back status words [ring_w][sigma]
+    uint64_t* ring;          // look-back status words [2^ring_log2][sigma]
     uint32_t* tile_ctr;
     uint32_t* err;
     uint64_t seq_base;       // ring sequence number of tile 0 of this round
-    uint32_t shift, bits, log2b, npi, ring_w;
+    uint32_t shift, bits, log2b, npi, ring_log2;
 };
 
 __device__ __forceinline__ uint64_t pack_status(uint64_t count, uint64_t flag, uint64_t epoch)
@@ -114,6 +114,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     for (uint32_t i = tid; i < WAVES * SMAX; i += NT) wh[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
+    const uint64_t g = a.seq_base + tile;         // ring sequence number of the tile
+    const uint32_t wlog = a.ring_log2;            // ring of 2^wlog tiles
+    const uint64_t wmask = (1ull << wlog) - 1;
     const uint64_t slot0 = (uint64_t)tile * E;
     // f is clamped so that a corrupt state can never index past pi
     const uint32_t f_in = OOP ? 0u : max(sigma, min(*a.f_in, a.npi));
@@ -242,22 +245,22 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
 
     // ---- publish counts and look back -------------------------------------------
     {
-        const uint64_t g = a.seq_base + tile, W = a.ring_w;
-        const uint64_t ep = g / W + 1;
-        uint64_t* myslot = a.ring + (g % W) * sigma;
+        const uint64_t ep = (g >> wlog) + 1;
+        uint64_t* myslot = a.ring + (g & wmask) * sigma;
         for (uint32_t d = tid; d < sigma; d += NT) {
             const uint32_t c = cnt[d];
             uint32_t spins = 0;
-            if (tile >= W) {
+            if ((uint64_t)tile > wmask) {
                 // the slot last held tile - W; readers of it are done once tile - W + 1
-                // is inclusive (a reader that still meets the old word restarts)
-                const uint64_t gp = g - W + 1, want = gp / W + 1;
-                const uint64_t* w = a.ring + (gp % W) * sigma + d;
+                // is inclusive (a reader that still meets the old word restarts).  That
+                // tile started W - 1 tiles earlier, so this wait almost never polls twice.
+                const uint64_t gp = g - wmask, want = (gp >> wlog) + 1;
+                const uint64_t* w = a.ring + (gp & wmask) * sigma + d;
                 for (;;) {
                     uint64_t s = ld_agent(w);
                     uint64_t e = s >> 34;
                     if (e > want || (e == want && ((s >> 32) & 3u) == kFlagInc)) break;
-                    if (++spins > kSpinLimit || ld_agent(a.err)) { raise_error(a.err, kErrSpin); break; }
+                    if (spin_give_up(++spins, a.err)) break;
                     spin_pause();
                 }
             }
@@ -268,8 +271,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
                 st_agent(myslot + d, pack_status(c, kFlagAgg, ep));
                 uint32_t k = tile - 1;
                 for (;;) {
-                    const uint64_t gk = a.seq_base + k, want = gk / W + 1;
-                    const uint64_t s = ld_agent(a.ring + (gk % W) * sigma + d);
+                    const uint64_t gk = a.seq_base + k, want = (gk >> wlog) + 1;
+                    const uint64_t s = ld_agent(a.ring + (gk & wmask) * sigma + d);
                     const uint64_t e = s >> 34, fl = (s >> 32) & 3u;
                     if (e == want && fl != 0) {
                         acc += (uint32_t)s;
@@ -282,7 +285,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
                         k = tile - 1;
                         continue;
                     }
-                    if (++spins > kSpinLimit || ld_agent(a.err)) { raise_error(a.err, kErrSpin); break; }
+                    if (spin_give_up(++spins, a.err)) break;
                     spin_pause();
                 }
                 st_agent(myslot + d, pack_status(acc + c, kFlagInc, ep));
@@ -330,10 +333,31 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
         for (uint32_t i = tid; i < E / 32; i += NT) fpref[i] = __popc(fmask[i]);
         __syncthreads();
         block_excl_scan<NT>(fpref, E / 32, tmp);
-        // resolve the physical block of every block the tile writes; publish draws
+        // Publish the tile's own draws first, for every digit, and only then wait for
+        // the blocks earlier tiles drew.  A wave runs its 64 digits in lock step, so
+        // a wait placed before the publications would hold all of them back and chain
+        // every tile to the publications of the one before it.
         for (uint32_t d = tid; d < sigma; d += NT) {
-            const uint32_t bs = base[d], c = cnt[d], q0 = bs >> log2b;
+            const uint32_t bs = base[d], q0 = bs >> log2b;
             const uint32_t nfill = nfw[d] >> 16, nwrite = nfw[d] & 0xFFFFu, t0 = tbo[d];
+            const uint32_t Sd = a.S[d];
+            for (uint32_t i = 1; i <= nfill; i++) {
+                const uint32_t lr = ((q0 + i) << log2b) - 1 - bs;
+                const uint32_t s = ls[excl[d] + lr];
+                const uint32_t r = fpref[s >> 5] + __popc(fmask[s >> 5] & ((1u << (s & 31)) - 1u));
+                const uint32_t h = sigma + F + r, L = Sd + q0 + i;
+                uint32_t phys = 0;
+                if (h < a.npi && L < a.npi) {
+                    phys = a.pi_old[h];
+                    st_agent(a.pi_new + L, phys);
+                } else {
+                    raise_error(a.err, kErrBounds);
+                }
+                if (i < nwrite) tbl[t0 + i] = phys;
+            }
+        }
+        for (uint32_t d = tid; d < sigma; d += NT) {
+            const uint32_t bs = base[d], c = cnt[d], q0 = bs >> log2b, t0 = tbo[d];
             const uint32_t Sd = a.S[d];
             if (c) {
                 uint32_t phys;
@@ -348,25 +372,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
                     for (;;) {
                         phys = ld_agent(a.pi_new + Sd + q0);
                         if (phys != kEmpty) break;
-                        if (++spins > kSpinLimit || ld_agent(a.err)) { raise_error(a.err, kErrSpin); phys = 0; break; }
+                        if (spin_give_up(++spins, a.err)) { phys = 0; break; }
                         spin_pause();
                     }
                 }
                 tbl[t0] = phys;
-            }
-            for (uint32_t i = 1; i <= nfill; i++) {
-                const uint32_t lr = ((q0 + i) << log2b) - 1 - bs;
-                const uint32_t s = ls[excl[d] + lr];
-                const uint32_t r = fpref[s >> 5] + __popc(fmask[s >> 5] & ((1u << (s & 31)) - 1u));
-                const uint32_t h = sigma + F + r, L = Sd + q0 + i;
-                uint32_t phys = 0;
-                if (h < a.npi && L < a.npi) {
-                    phys = a.pi_old[h];
-                    st_agent(a.pi_new + L, phys);
-                } else {
-                    raise_error(a.err, kErrBounds);
-                }
-                if (i < nwrite) tbl[t0 + i] = phys;
             }
             adj[d] = bs - excl[d];
             tbo[d] = t0 - q0;

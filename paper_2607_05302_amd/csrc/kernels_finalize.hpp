@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_fin_compact(FinArgs<KB, VB> a, const ui
     for (uint32_t w = cfirst + tid; w < c; w += 256) {
         uint32_t spins = 0;
         while (ld_agent(flags + w) == 0u) {
-            if (++spins > kSpinLimit || ld_agent(a.err)) { raise_error(a.err, kErrSpin); break; }
+            if (spin_give_up(++spins, a.err)) break;
             spin_pause();
         }
     }

@@ -30,7 +30,7 @@ radsort_stats g_stats{};
         }                                            \
     } while (0)
 
-constexpr uint32_t kRingWords = 1u << 19;  // look-back ring: ring_w * sigma status words
+constexpr uint32_t kRingWords = 1u << 19;  // look-back ring: 2^ring_log2 * sigma status words
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -52,7 +52,7 @@ struct Geo {
     uint64_t n = 0;
     uint32_t kb = 0, vb = 0, bits = 0, sigma = 0, nt = 0, b = 0, log2b = 0;
     uint64_t nb = 0;
-    uint32_t npi = 0, E = 0, tiles = 0, ring_w = 0;
+    uint32_t npi = 0, E = 0, tiles = 0, ring_w = 0, ring_log2 = 0;
 };
 
 // Workspace regions (byte offsets), each 256-byte aligned.
@@ -98,7 +98,8 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     // input slots of a round: at most (floor(n/b) + sigma) blocks of b
     uint64_t slots = (g.nb + g.sigma) << g.log2b;
     g.tiles = (uint32_t)((slots + g.E - 1) / g.E);
-    g.ring_w = std::max<uint32_t>(256u, kRingWords / g.sigma);
+    g.ring_w = std::max<uint32_t>(256u, kRingWords / g.sigma);  // powers of two
+    g.ring_log2 = ilog2(g.ring_w);
     return RADSORT_OK;
 }
 
@@ -322,7 +323,7 @@ template <int KB, int VB> struct Ops {
         a.bits = g.bits;
         a.log2b = g.log2b;
         a.npi = g.npi;
-        a.ring_w = g.ring_w;
+        a.ring_log2 = g.ring_log2;
         launch_fill(a.tile_ctr, 1, 0, s);
         g_timer.mark(kRoundBegin, r, s);
         launch_round_t<KB, VB, false>(g, a, s);
@@ -422,7 +423,7 @@ template <int KB, int VB> struct Ops {
             a.shift = g.bits * (g.nt - 1 - t);
             a.bits = g.bits;
             a.log2b = g.log2b;
-            a.ring_w = g.ring_w;
+            a.ring_log2 = g.ring_log2;
             g_timer.mark(kRoundBegin, r, s);
             launch_round_t<KB, VB, true>(g, a, s);
             g_timer.mark(kRoundEnd, r, s);
