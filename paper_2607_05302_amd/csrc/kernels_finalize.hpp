@@ -29,7 +29,7 @@
 
 namespace rs {
 
-constexpr uint32_t kFinJob = 1024;      // nodes per job of F1
+constexpr uint32_t kFinJob = 2048;      // nodes per job of F1
 constexpr uint32_t kFinCols = 256;      // columns of a block moved by one F1 workgroup
 constexpr uint32_t kFinDepth = 8;       // loads in flight per thread in F1
 constexpr uint32_t kScanTile = 4096;    // elements per workgroup of the device scan
@@ -37,8 +37,9 @@ constexpr uint32_t kGarbage = 0x80000000u;
 
 inline uint64_t fin_align(uint64_t x) { return (x + 255) / 256 * 256; }
 
-// Bytes of finalize scratch: eight n_pi-word arrays, the scan's block sums, the
-// F2 chunk flags and two temporary blocks per F1 job.
+// Bytes of finalize scratch: six n_pi-word arrays (two more reuse the second pi
+// buffer and the block-length array, which finalize no longer needs), the scan's
+// block sums, the F2 chunk flags and two temporary blocks per F1 job.
 constexpr uint32_t kCompactMin = 4096;  // smallest F2 chunk (elements)
 
 // F2 chunk flags (one per chunk) plus a counter
@@ -51,7 +52,7 @@ inline uint64_t fin_scratch_bytes(uint32_t npi, uint64_t n, uint32_t b, uint32_t
 {
     uint64_t jobs = (npi + kFinJob - 1) / kFinJob;
     uint64_t sums = (npi + kScanTile - 1) / kScanTile + 1;
-    return 8 * fin_align(4ull * npi) + fin_align(4 * sums) + fin_align(4 * fin_flag_words(npi, n)) +
+    return 6 * fin_align(4ull * npi) + fin_align(4 * sums) + fin_align(4 * fin_flag_words(npi, n)) +
            fin_align(2 * jobs * (uint64_t)b * elem_bytes);
 }
 
@@ -71,7 +72,8 @@ struct FinArgs {
     uint32_t sigma, log2b, npi;
     uint32_t* err;
     uint8_t* scratch;
-    uint32_t* spare_pi;
+    uint32_t* spare_pi;  // the other pi buffer (n_pi words), free during finalize
+    uint32_t* spare_blen;  // the block-length array (n_pi words), free during finalize
 };
 
 struct FinArrays {
@@ -80,23 +82,24 @@ struct FinArrays {
     uint8_t* temps;
 };
 
-inline FinArrays fin_arrays(uint8_t* s, uint32_t npi, uint64_t n)
+inline FinArrays fin_arrays(uint8_t* s, uint32_t npi, uint64_t n, uint32_t* spare_pi,
+                            uint32_t* spare_blen)
 {
     FinArrays a;
     uint64_t w = fin_align(4ull * npi);
-    a.nxt = (uint32_t*)(s + 0 * w);
-    a.j0 = (uint32_t*)(s + 1 * w);
-    a.j1 = (uint32_t*)(s + 2 * w);
-    a.v0 = (uint32_t*)(s + 3 * w);
-    a.v1 = (uint32_t*)(s + 4 * w);
-    a.o0 = (uint32_t*)(s + 5 * w);
-    a.o1 = (uint32_t*)(s + 6 * w);
-    a.ord = (uint32_t*)(s + 7 * w);
-    a.sums = (uint32_t*)(s + 8 * w);
+    a.nxt = spare_pi;
+    a.ord = spare_blen;
+    a.j0 = (uint32_t*)(s + 0 * w);
+    a.j1 = (uint32_t*)(s + 1 * w);
+    a.v0 = (uint32_t*)(s + 2 * w);
+    a.v1 = (uint32_t*)(s + 3 * w);
+    a.o0 = (uint32_t*)(s + 4 * w);
+    a.o1 = (uint32_t*)(s + 5 * w);
+    a.sums = (uint32_t*)(s + 6 * w);
     uint64_t sums = (npi + kScanTile - 1) / kScanTile + 1;
-    a.flags = (uint32_t*)(s + 8 * w + fin_align(4 * sums));
+    a.flags = (uint32_t*)(s + 6 * w + fin_align(4 * sums));
     a.nflags = fin_flag_words(npi, n);
-    a.temps = s + 8 * w + fin_align(4 * sums) + fin_align(4 * a.nflags);
+    a.temps = s + 6 * w + fin_align(4 * sums) + fin_align(4 * a.nflags);
     return a;
 }
 
@@ -505,7 +508,7 @@ template <int KB, int VB>
 int finalize_parallel(FinArgs<KB, VB>& a, hipStream_t s)
 {
     const uint32_t npi = a.npi, b = 1u << a.log2b;
-    FinArrays f = fin_arrays(a.scratch, npi, a.n);
+    FinArrays f = fin_arrays(a.scratch, npi, a.n, a.spare_pi, a.spare_blen);
     const uint32_t grid = std::min<uint32_t>((npi + 255) / 256, 8192);
     // F1: cycles
     uint32_t *J[2] = {f.j0, f.j1}, *Vv[2] = {f.v0, f.v1}, *O[2] = {f.o0, f.o1};

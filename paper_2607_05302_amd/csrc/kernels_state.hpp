@@ -104,7 +104,8 @@ __global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
                         typename UInt<KB>::T* __restrict__ Tk,
                         typename Payload<VB>::T* __restrict__ Tv, uint64_t n, uint32_t log2b,
                         uint32_t sigma, uint32_t npi, uint32_t* __restrict__ pi,
-                        uint32_t* __restrict__ pi_next)
+                        uint32_t* __restrict__ pi_next, uint32_t* __restrict__ blen,
+                        uint64_t* __restrict__ opened)
 {
     const uint64_t nb = n >> log2b, tail = n - (nb << log2b);
     const uint32_t f = sigma + (uint32_t)nb + 1;
@@ -117,6 +118,9 @@ __global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
             else v = sigma + (L - (f - 1));
             pi[L] = v;
             pi_next[L] = kEmpty;
+            // used lengths: full blocks, and the tail as logical f - 1 (Alg. 4)
+            blen[L] = L + 1 == f ? (uint32_t)tail : (1u << log2b);
+            if (L < sigma) opened[L] = 0;
         }
         if (i < tail) {
             uint64_t dst = ((uint64_t)sigma << log2b) + i;
@@ -133,13 +137,18 @@ __global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
 // c .. c + sigma - 1 and the rest keeps its place, with c = f_out - sigma the
 // number of blocks drawn.  Each entry of pi_old is read by the thread that owns
 // it, which then resets it to "unset" for the next round.
+// It also writes the used length of every logical block for the next round:
+// b, or the length recorded in P for the buckets' last blocks.
 __global__ void k_fixup(uint32_t* __restrict__ pi_old, uint32_t* __restrict__ pi_new,
                         const uint32_t* __restrict__ S, const uint32_t* __restrict__ f_out,
-                        uint32_t sigma, uint32_t npi)
+                        const uint32_t* __restrict__ Pidx, const uint32_t* __restrict__ Plen,
+                        uint32_t* __restrict__ blen, uint64_t* __restrict__ opened,
+                        uint32_t sigma, uint32_t log2b, uint32_t npi)
 {
     const uint32_t c = *f_out - sigma;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < npi;
          j += gridDim.x * blockDim.x) {
+        if (j < sigma) opened[j] = 0;  // per-bucket latest draw, for the next round
         uint32_t v = pi_old[j];
         if (j < sigma) {
             if (S[j] < npi) pi_new[S[j]] = v;
@@ -147,6 +156,13 @@ __global__ void k_fixup(uint32_t* __restrict__ pi_old, uint32_t* __restrict__ pi
         else if (j >= c && j < c + sigma) pi_new[j - c] = v;
         else if (j >= c + sigma) pi_new[j] = v;
         pi_old[j] = kEmpty;
+        uint32_t lo = 0, hi = sigma;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (Pidx[mid] < j) lo = mid + 1;
+            else hi = mid;
+        }
+        blen[j] = (lo < sigma && Pidx[lo] == j) ? Plen[lo] : (1u << log2b);
     }
 }
 

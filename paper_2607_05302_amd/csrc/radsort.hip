@@ -4,8 +4,12 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <utility>
 
 #include "../../include/radsort.h"
 #include "common.hpp"
@@ -57,7 +61,8 @@ struct Geo {
 
 // Workspace regions (byte offsets), each 256-byte aligned.
 struct Layout {
-    uint64_t Tk, Tv, pi0, pi1, hist, S, Pidx, Plen, f, est, ctr, ring, fin, alt_k, alt_v;
+    uint64_t Tk, Tv, pi0, pi1, blen, opened, hist, S, Pidx, Plen, f, est, ctr, agg, ring, fin,
+        alt_k, alt_v;
     uint64_t ring_bytes, fin_bytes, total;
 };
 
@@ -121,6 +126,8 @@ Layout make_layout(const Geo& g, bool oop)
         L.Tv = take(2 * sig * g.b * g.vb);
         L.pi0 = take(4ull * g.npi);
         L.pi1 = take(4ull * g.npi);
+        L.blen = take(4ull * g.npi);
+        L.opened = take(8ull * g.sigma);
     } else {
         L.alt_k = take(g.n * g.kb);
         L.alt_v = take(g.n * g.vb);
@@ -132,6 +139,7 @@ Layout make_layout(const Geo& g, bool oop)
     L.f = take(4 * (nt + 1));
     L.est = take(4 * nt * sig);
     L.ctr = take(4 * (nt + 8));
+    L.agg = take(2ull * g.ring_w * sig);
     L.ring_bytes = 8ull * g.ring_w * sig;
     L.fin_bytes = oop ? 0 : finalize_bytes(g);
     L.ring = take(std::max(L.ring_bytes, L.fin_bytes));  // finalize reuses the ring
@@ -232,7 +240,6 @@ struct radsort_state {
         return PlanPtrs{u32(L.S), u32(L.Pidx), u32(L.Plen), u32(L.f), u32(L.est)};
     }
     uint32_t* err() const { return u32(L.ctr) + g.nt; }
-    uint32_t* tile_ctr(uint32_t r) const { return u32(L.ctr) + r; }
 };
 
 namespace {
@@ -259,19 +266,52 @@ int launch_plan(const Geo& g, const uint32_t* hist, PlanPtrs p, hipStream_t s)
     return RADSORT_OK;
 }
 
+// Workgroups of `kern` that fit on the device at once (cached per device).
+int resident_capacity(const void* kern, uint32_t threads)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, kern});
+    if (it != cache.end()) return it->second;
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, (int)threads, 0) != hipSuccess)
+        return 0;
+    cache[{dev, kern}] = cus * per;
+    return cus * per;
+}
+
+// The round kernel is persistent: at most as many workgroups as fit at once, all
+// resident (cooperative launch), each taking tiles in grid-stride order.
+template <typename Args>
+int launch_persistent(const void* kern, uint32_t tiles, uint32_t threads, Args& a, hipStream_t s)
+{
+    const int cap = resident_capacity(kern, threads);
+    if (cap <= 0) return RADSORT_E_DEVICE;
+    const uint32_t grid = std::min<uint32_t>(tiles, (uint32_t)cap);
+    static const bool verbose = getenv("RADSORT_VERBOSE") != nullptr;
+    if (verbose)
+        fprintf(stderr, "radsort: persistent launch %u workgroups x %u threads for %u tiles\n",
+                grid, threads, tiles);
+    void* args[] = {(void*)&a};
+    RS_HIP(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(threads), args, 0, s));
+    return RADSORT_OK;
+}
+
 template <int KB, int VB, bool OOP>
 int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s)
 {
     constexpr int W = TileCfg<KB, VB>::WAVES, I = TileCfg<KB, VB>::ITEMS;
-    const uint32_t grid = OOP ? (uint32_t)((g.n + g.E - 1) / g.E) : g.tiles;
-    if (grid == 0) return RADSORT_OK;
-    if (g.bits == 8)
-        hipLaunchKernelGGL((k_round<KB, VB, OOP, 8, 256, W, I>), dim3(grid), dim3(64 * W), 0, s, a);
-    else if (g.bits <= 8)
-        hipLaunchKernelGGL((k_round<KB, VB, OOP, 0, 256, W, I>), dim3(grid), dim3(64 * W), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_round<KB, VB, OOP, 0, 2048, W, I>), dim3(grid), dim3(64 * W), 0, s, a);
-    return RADSORT_OK;
+    const uint32_t tiles = OOP ? (uint32_t)((g.n + g.E - 1) / g.E) : g.tiles;
+    if (tiles == 0) return RADSORT_OK;
+    const void* kern;
+    if (g.bits == 8) kern = (const void*)&k_round<KB, VB, OOP, 8, 256, W, I>;
+    else if (g.bits <= 8) kern = (const void*)&k_round<KB, VB, OOP, 0, 256, W, I>;
+    else kern = (const void*)&k_round<KB, VB, OOP, 0, 2048, W, I>;
+    return launch_persistent(kern, tiles, 64 * W, a, s);
 }
 
 template <int KB, int VB> struct Ops {
@@ -290,7 +330,8 @@ template <int KB, int VB> struct Ops {
         uint32_t grid = (uint32_t)std::min<uint64_t>((work + 255) / 256, 4096);
         hipLaunchKernelGGL((k_setup<KB, VB>), dim3(grid), dim3(256), 0, s, (K*)st->keys,
                            (V*)st->vals, (K*)(st->ws + st->L.Tk), (V*)(st->ws + st->L.Tv), g.n,
-                           g.log2b, g.sigma, g.npi, st->pi(0), st->pi(1));
+                           g.log2b, g.sigma, g.npi, st->pi(0), st->pi(1), st->u32(st->L.blen),
+                           (uint64_t*)(st->ws + st->L.opened));
         g_timer.mark(kSetupEnd, 0, s);
         st->cur = 0;
         st->rounds_done = 0;
@@ -311,12 +352,12 @@ template <int KB, int VB> struct Ops {
         a.Tv = (V*)(st->ws + st->L.Tv);
         a.pi_old = st->pi(st->cur);
         a.pi_new = st->pi(st->cur ^ 1);
-        a.Pidx = st->u32(st->L.Pidx) + r * g.sigma;
-        a.Plen = st->u32(st->L.Plen) + r * g.sigma;
+        a.blen = st->u32(st->L.blen);
         a.f_in = st->u32(st->L.f) + r;
         a.S = st->u32(st->L.S) + r * g.sigma;
+        a.opened = (uint64_t*)(st->ws + st->L.opened);
         a.ring = (uint64_t*)(st->ws + st->L.ring);
-        a.tile_ctr = st->tile_ctr(r);
+        a.agg = (uint16_t*)(st->ws + st->L.agg);
         a.err = st->err();
         a.seq_base = st->seq;
         a.shift = g.bits * (g.nt - 1 - t);
@@ -324,13 +365,17 @@ template <int KB, int VB> struct Ops {
         a.log2b = g.log2b;
         a.npi = g.npi;
         a.ring_log2 = g.ring_log2;
-        launch_fill(a.tile_ctr, 1, 0, s);
+        launch_fill((uint32_t*)a.agg, (uint64_t)g.ring_w * g.sigma / 2, 0, s);
         g_timer.mark(kRoundBegin, r, s);
-        launch_round_t<KB, VB, false>(g, a, s);
+        int rc = launch_round_t<KB, VB, false>(g, a, s);
+        if (rc) return rc;
         g_timer.mark(kRoundEnd, r, s);
         uint32_t grid = (uint32_t)std::min<uint64_t>((g.npi + 255) / 256, 4096);
         hipLaunchKernelGGL(k_fixup, dim3(grid), dim3(256), 0, s, st->pi(st->cur),
-                           st->pi(st->cur ^ 1), a.S, st->u32(st->L.f) + r + 1, g.sigma, g.npi);
+                           st->pi(st->cur ^ 1), a.S, st->u32(st->L.f) + r + 1,
+                           st->u32(st->L.Pidx) + (r + 1) * g.sigma,
+                           st->u32(st->L.Plen) + (r + 1) * g.sigma, st->u32(st->L.blen),
+                           a.opened, g.sigma, g.log2b, g.npi);
         g_timer.mark(kFixupEnd, r, s);
         st->cur ^= 1;
         st->rounds_done++;
@@ -370,6 +415,7 @@ template <int KB, int VB> struct Ops {
         a.err = st->err();
         a.scratch = st->ws + st->L.fin;
         a.spare_pi = st->pi(st->cur ^ 1);
+        a.spare_blen = st->u32(st->L.blen);
         g_timer.mark(kFinBegin, 0, s);
         int rc = finalize_parallel<KB, VB>(a, s);
         g_timer.mark(kFinEnd, 0, s);
@@ -417,15 +463,17 @@ template <int KB, int VB> struct Ops {
             a.est = p.est + r * g.sigma;
             a.n = g.n;
             a.ring = (uint64_t*)(ws + L.ring);
-            a.tile_ctr = ctr + r;
+            a.agg = (uint16_t*)(ws + L.agg);
             a.err = ctr + g.nt;
             a.seq_base = (uint64_t)r * tiles;
             a.shift = g.bits * (g.nt - 1 - t);
             a.bits = g.bits;
             a.log2b = g.log2b;
             a.ring_log2 = g.ring_log2;
+            launch_fill((uint32_t*)a.agg, (uint64_t)g.ring_w * g.sigma / 2, 0, s);
             g_timer.mark(kRoundBegin, r, s);
-            launch_round_t<KB, VB, true>(g, a, s);
+            int rc = launch_round_t<KB, VB, true>(g, a, s);
+            if (rc) return rc;
             g_timer.mark(kRoundEnd, r, s);
         }
         g_timer.mark(kFinBegin, 0, s);
