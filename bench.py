@@ -172,6 +172,7 @@ def main():
             "value": n / (np.mean(otimes) / 1e3), "unit": "keys/s",
             "ms_per_step": float(np.mean(otimes)), "min_ms": float(np.min(otimes)),
             "round_ms_mean": float(np.mean([np.mean(s["round_ms"]) for s in ostats])),
+            "count_ms_mean": float(np.mean([np.mean(s["count_ms"]) for s in ostats])),
             "peak_extra_bytes": oop_bytes,
             "peak_extra_frac_of_input": oop_bytes / (n * (kb + vb)),
         }
@@ -221,6 +222,7 @@ def main():
         "phases_ms": {
             "setup": float(np.mean([s["setup_ms"] for s in stats])),
             "rounds": round_ms,
+            "supertile_counts": [float(np.mean([s["count_ms"][r] for s in stats])) for r in range(4)],
             "fixup_total": float(np.mean([s["fixup_ms"] for s in stats])),
             "finalize": float(np.mean([s["finalize_ms"] for s in stats])),
         },

@@ -67,6 +67,7 @@ typedef struct radsort_stats {
     uint32_t timed;             /* 1 when the fields below are valid */
     float setup_ms;             /* histograms, plan and setup (Alg. 4) */
     float round_ms[RADSORT_MAX_ROUNDS]; /* the sort-round kernel of each round (Alg. 5) */
+    float count_ms[RADSORT_MAX_ROUNDS]; /* each round's super-tile digit counts and their scan */
     float fixup_ms;             /* all fixup kernels (Alg. 6) and counter resets */
     float finalize_ms;          /* finalize (Alg. 7); for the baseline: a final copy-back */
     float total_ms;             /* first event to last event */

@@ -50,7 +50,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("workspace_bytes", ctypes.c_uint64), ("input_bytes", ctypes.c_uint64),
                 ("rounds", ctypes.c_uint32), ("error_bits", ctypes.c_uint32),
                 ("timed", ctypes.c_uint32), ("setup_ms", ctypes.c_float),
-                ("round_ms", ctypes.c_float * MAX_ROUNDS), ("fixup_ms", ctypes.c_float),
+                ("round_ms", ctypes.c_float * MAX_ROUNDS),
+                ("count_ms", ctypes.c_float * MAX_ROUNDS), ("fixup_ms", ctypes.c_float),
                 ("finalize_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
 
 
@@ -206,6 +207,7 @@ def last_stats() -> dict:
            "rounds": s.rounds, "error_bits": s.error_bits, "timed": bool(s.timed)}
     if s.timed:
         out.update(setup_ms=s.setup_ms, round_ms=[s.round_ms[i] for i in range(s.rounds)],
+                   count_ms=[s.count_ms[i] for i in range(s.rounds)],
                    fixup_ms=s.fixup_ms, finalize_ms=s.finalize_ms, total_ms=s.total_ms)
     return out
 

@@ -7,17 +7,23 @@
 // resident at once; workgroup w takes tiles w, w + G, w + 2G, ... (G workgroups).
 // A tile waits only on lower tiles, and the lowest unfinished tile has all of its
 // predecessors finished, so the waits always end.  (A shared tile counter would
-// serialise the launch on one atomic: about 11 ns per tile on MI355X.)
+// serialise the launch on one atomic: about 11 ns per tile on MI355X.)  Tiles
+// come in super-tiles of 2^st_log2; a pass before the kernel gives the digit
+// counts before every super-tile (kernels_prefix.hpp).
 //
-//   1  read the tile's blocks through pi (keys and payload);
+//   1  read the tile's blocks through pi (keys and payload) into registers; this
+//      is issued while the workgroup still works on its previous tile;
 //   2  stable rank inside the tile, per wave: for each group of 64 slots, every
 //      lane ORs its lane bit into a wave-private LDS word of its digit and reads
 //      the word back, which gives the lanes holding the same digit; lower lanes
 //      of that set come first (slot order).  Per-wave digit counts in LDS;
-//   3  stage the tile in LDS in (digit, slot) order;
-//   4  publish the tile's digit counts, then decoupled look-back over earlier
-//      tiles (reading up to kLookbackWin predecessors per step) gives base[d],
-//      the number of digit-d elements before the tile;
+//   3  publish the tile's digit counts, and stage the tile in LDS in (digit,
+//      slot) order;
+//   4  a decoupled look-back over the earlier tiles of the super-tile (up to
+//      kLookbackWin per step, so usually one step) plus the super-tile's start
+//      gives base[d], the number of digit-d elements before the tile.  A
+//      look-back over all earlier tiles would chain every tile of the launch to
+//      the one before it;
 //   5  global rank r = base[d] + local rank.  Bucket d's block q holds ranks
 //      [q b, (q+1) b) and sits at logical index S[d] + q (Alg. 6).  Block q >= 1
 //      is drawn when rank q b - 1 is written (eager allocation, Alg. 5).  Blocks
@@ -25,17 +31,22 @@
 //      algorithm draws them: the first blocks of the buckets are pool entries
 //      0..sigma-1, block draws number sigma, sigma+1, ... in slot order.  A tile
 //      finds its draws' pool indices from base[] (draws in earlier tiles are
-//      sum_d floor(base[d]/b)) plus an in-tile prefix count in slot order, and
-//      publishes pi_new[S[d] + q] for each draw;
+//      F = sum_d floor(base[d]/b)) plus an in-tile prefix count in slot order,
+//      and publishes pi_new[S[d] + q] for each draw.  A bucket's block that holds
+//      the tile's first elements of that digit was drawn by an earlier tile: its
+//      pi_new entry is requested as soon as base[] is known and waited for only
+//      after the tile's own draws are out (waiting first would chain each tile
+//      to the draws of the one before);
 //   6  write each element to blockat(pi_new[S[d] + q]) + (r mod b).
 //
 // Why a drawn block is never overwritten before it is read (the GPU form of
-// Lemma 1): a tile draws only after its look-back, when every tile up to it has
-// published its counts, which each tile does only after its loads returned.
-// Draws up to tile k number at most sum_d floor(ranks_d / b) <= floor(E_k / b),
-// with E_k the elements of tiles <= k, and these tiles cover at least
-// ceil(E_k / b) logical blocks, so every drawn pool index names a head-start
-// block or a block already consumed.
+// Lemma 1): draws up to tile k number at most sum_d floor(ranks_d / b) <=
+// floor(E_k / b), with E_k the elements of tiles <= k, and these tiles cover at
+// least ceil(E_k / b) logical blocks, so every drawn pool index names a
+// head-start block or an input block of a tile <= k.  A tile publishes its counts
+// only after its loads returned; before writing into drawn blocks a tile waits
+// for the counts of their tiles (those of its own super-tile it has already
+// read in the look-back) or for their done word.
 //
 // The pool order, and with it pi, P and f after every round, is the same as in
 // the sequential algorithm.
@@ -45,23 +56,23 @@
 
 namespace rs {
 
-constexpr int kLookbackWin = 4;  // predecessors read per look-back step
+constexpr int kLookbackWin = 16;  // predecessors read per look-back step
 
-// 16-bit tile-count words of the look-back: bits 0-12 the tile's count of a digit,
-// bit 13 set once the tile's inclusive prefix is in the 64-bit ring, bits 14-15
-// the tile's round-local epoch mod 4.  The array is zeroed before each round, so a
-// slot holds the epoch before, at or after the one a reader expects: the three are
-// told apart mod 4.  Reading these words instead of 64-bit ones cuts the
-// look-back's coherent traffic by four; the 64-bit word is read only once, for
-// the nearest tile whose hint bit is set.
-constexpr uint32_t kAggHint = 1u << 13;
-__device__ __forceinline__ uint16_t ld_agent16(const uint16_t* p)
+// Look-back words.  cnt[slot][d] holds a tile's count of digit d in bits 0-30
+// and, in bit 31, the parity of the tile's ring epoch (floor(tile / W)) inverted,
+// so that the zero-filled array reads as "not yet" for epoch 0.  done[slot] holds
+// tile + 1 once the tile has finished its look-back.  Slot = tile mod W.
+//
+// A slot is reused by tile T only after every tile of the super-tile of T - W,
+// from T - W on, is done: those are the only readers of its counts, and T - W
+// published before it was done.  So a reader of a predecessor's slot finds
+// either that tile's word or the one before it (W tiles earlier), and the parity
+// bit tells them apart.  done[] only grows within a slot, so done[o mod W] > o
+// says that tile o is done, hence that its loads have returned.
+constexpr uint32_t kCntMask = 0x7FFFFFFFu;
+__device__ __forceinline__ uint32_t epoch_bit(uint32_t tile, uint32_t wlog)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent16(uint16_t* p, uint16_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (~(tile >> wlog) & 1u) << 31;
 }
 
 template <int KB, int VB>
@@ -80,17 +91,14 @@ struct TileArgs {
     uint64_t* opened;        // per bucket: (q << 32 | physical) of its latest drawn block
     const uint32_t* est;     // out-of-place only: element start of each bucket
     uint64_t n;              // out-of-place only
-    uint64_t* ring;          // inclusive prefixes [2^ring_log2][sigma]: count | flag | epoch
-    uint16_t* agg;           // tile counts [2^ring_log2][sigma]: count | hint | tag, zeroed per round
+    uint32_t* agg;           // tile counts [2^ring_log2][sigma], zeroed per round
+    uint32_t* done;          // [2^ring_log2]: tile + 1 once done, zeroed per round
+    const uint32_t* stbase;  // [super-tile][sigma]: digit counts before each super-tile
     uint32_t* err;
-    uint64_t seq_base;       // ring sequence number of tile 0 of this round
     uint32_t shift, bits, log2b, npi, ring_log2;
+    uint32_t st_log2;        // tiles per super-tile: 2^st_log2
 };
 
-__device__ __forceinline__ uint64_t pack_status(uint64_t count, uint64_t flag, uint64_t epoch)
-{
-    return count | (flag << 32) | (epoch << 34);
-}
 
 template <int KB, int VB, bool OOP, int FB, int SMAX, int WAVES, int ITEMS>
 __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
@@ -106,7 +114,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     constexpr int PTAB = OR_RANK ? 4 * TBL : 0;  // words of the pointer table
     constexpr int UNI = (E / 2 + 2 * SMAX) > PTAB ? (E / 2 + 2 * SMAX) : PTAB;
     static_assert(E <= 65536, "slot indices are 16-bit");
-    static_assert(E < 8192, "tile counts fit the 13-bit field of the look-back words");
     static_assert(WAVES >= 4, "per-digit scratch reuses the per-wave counts");
     static_assert(!OR_RANK || E * KB >= WAVES * SMAX * 8, "OR tables live in the key stage");
 
@@ -121,9 +128,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     __shared__ __align__(16) uint32_t wh[WAVES * SMAX];  // per-wave counts, later per-digit data
     __shared__ uint32_t tbo[SMAX];
     __shared__ uint32_t tphys[TBL];
+    __shared__ uint32_t pool[OOP ? 1 : TBL];     // physical blocks of the tile's draws
     __shared__ uint32_t fmask[E / 32], fpref[E / 32];
     __shared__ uint32_t bphys[MAXBLK], blen[MAXBLK];
-    __shared__ uint32_t tmp[NT / 64 + 1];
+    __shared__ uint32_t tmp[2 * (NT / 64) + 2];
 
     uint16_t* ls = (uint16_t*)uni;               // slot of each staged element
     uint32_t* cnt = uni + E / 2;
@@ -131,6 +139,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
 
     const uint32_t wlog = a.ring_log2;
     const uint64_t wmask = (1ull << wlog) - 1;
+    const uint32_t mst = 1u << a.st_log2;  // tiles per super-tile
     // f is clamped so that a corrupt state can never index past pi
     const uint32_t f_in = OOP ? 0u : max(sigma, min(*a.f_in, a.npi));
     uint64_t nslots;
@@ -160,62 +169,68 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             }
         }
     };
+    // issue the loads of tile t into (kn, vn); block info of t must be in LDS
+    K kn[ITEMS];
+    V vn[ITEMS];
+    bool vld[ITEMS];
+    auto load_tile = [&](uint32_t t) {
+        const uint64_t slot0 = (uint64_t)t * E;
+        const uint32_t blk0 = (uint32_t)(slot0 >> log2b);
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            const uint64_t gs = slot0 + wave * SEG + j * 64 + lane;
+            bool valid;
+            const K* kp;
+            const V* vp = nullptr;
+            if constexpr (OOP) {
+                valid = gs < a.n;
+                kp = a.Ak + gs;
+                if constexpr (VB != 0) vp = a.Av + gs;
+            } else {
+                const uint32_t bi = (uint32_t)(gs >> log2b) - blk0;
+                const uint32_t off = (uint32_t)gs & (b - 1);
+                valid = t < ntiles && off < blen[bi];
+                const uint32_t phys = bphys[bi];
+                kp = blockat(a.Ak, a.Tk, phys, two_sigma, log2b) + off;
+                if constexpr (VB != 0) vp = blockat(a.Av, a.Tv, phys, two_sigma, log2b) + off;
+            }
+            vld[j] = valid;
+            kn[j] = valid ? *kp : (K)0;
+            if constexpr (VB != 0) vn[j] = valid ? *vp : (V)0;
+        }
+    };
     block_info(blockIdx.x);
+    __syncthreads();
+    load_tile(blockIdx.x);
 
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    __syncthreads();  // the previous tile is done with LDS; this tile's block info is in
-    for (uint32_t i = lane; i < SMAX; i += 64) wh[wave * SMAX + i] = 0;
-    if constexpr (OR_RANK) {
-        uint64_t* myor = (uint64_t*)lk + wave * SMAX;
-        for (uint32_t i = lane; i < SMAX; i += 64) myor[i] = 0;
-    }
-    const uint64_t g = a.seq_base + tile;  // ring sequence number of the tile
-    const uint64_t slot0 = (uint64_t)tile * E;
-
-    const uint32_t blk0 = (uint32_t)(slot0 >> log2b);
-
-    // ---- load --------------------------------------------------------------------------
     K key[ITEMS];
     V val[ITEMS];
     uint32_t rk[ITEMS];  // wave-local rank << 12 | digit, or ~0 for an empty slot
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        const uint32_t s = wave * SEG + j * 64 + lane;
-        const uint64_t gs = slot0 + s;
-        bool valid;
-        const K* kp;
-        const V* vp = nullptr;
-        if constexpr (OOP) {
-            valid = gs < a.n;
-            kp = a.Ak + gs;
-            if constexpr (VB != 0) vp = a.Av + gs;
-        } else {
-            const uint32_t bi = (uint32_t)(gs >> log2b) - blk0;
-            const uint32_t off = (uint32_t)gs & (b - 1);
-            valid = off < blen[bi];
-            const uint32_t phys = bphys[bi];
-            kp = blockat(a.Ak, a.Tk, phys, two_sigma, log2b) + off;
-            if constexpr (VB != 0) vp = blockat(a.Av, a.Tv, phys, two_sigma, log2b) + off;
-        }
-        key[j] = valid ? *kp : (K)0;
-        if constexpr (VB != 0) val[j] = valid ? *vp : (V)0;
-        rk[j] = valid ? 0u : ~0u;
+        key[j] = kn[j];
+        if constexpr (VB != 0) val[j] = vn[j];
+        rk[j] = vld[j] ? 0u : ~0u;
     }
+    __syncthreads();  // the previous tile is done with LDS
+    for (uint32_t i = lane; i < SMAX; i += 64) wh[wave * SMAX + i] = 0;
+    if constexpr (OR_RANK) {
+        uint64_t* myor = (uint64_t*)lk + wave * SMAX;
+        for (uint32_t i = lane; i < SMAX; i += 64) myor[i] = 0;
+    }
+    // the next tile's block info: its loads are issued once this tile is staged
+    block_info(tile + gridDim.x);
 
-    // The ring slot of this tile last held tile - W; its readers are done once tile
-    // - W + 1 is inclusive (a reader that still meets the old word starts over).
-    // That tile started W - 1 tiles earlier, so this wait almost never polls twice.
-    // It is checked here so that its latency overlaps the loads.
+    // Reuse of this tile's ring slot (see the look-back words above); the tiles
+    // waited for started W tiles earlier, so the wait almost never polls twice.
     if ((uint64_t)tile > wmask) {
-        const uint32_t tp = tile - (uint32_t)wmask;  // tile - W + 1
-        const uint32_t tag = ((tp >> wlog) + 1) & 3u;
-        for (uint32_t d = tid; d < sigma; d += NT) {
-            const uint16_t* w = a.agg + (uint64_t)(tp & wmask) * sigma + d;
+        const uint32_t q = tile - (uint32_t)wmask - 1;           // tile - W
+        const uint32_t qend = min((q | (mst - 1)) + 1, ntiles);  // end of its super-tile
+        for (uint32_t j = q + tid; j < qend; j += NT) {
+            const uint32_t* w = a.done + (j & wmask);
             uint32_t spins = 0;
-            for (;;) {
-                const uint32_t s = ld_agent16(w);
-                const uint32_t t = s >> 14;
-                if (t == ((tag + 1) & 3u) || (t == tag && (s & kAggHint))) break;
+            while (ld_agent(w) <= j) {
                 if (spin_give_up(++spins, a.err)) break;
                 spin_pause();
             }
@@ -260,11 +275,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             }
         }
     }
+    // Every load of the tile has returned (the payload is not read before staging,
+    // so wait for it here): from the counts' publication on, other tiles may
+    // reuse the tile's blocks.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    // every wave has issued its loads: fetch the next tile's block info meanwhile
-    block_info(tile + gridDim.x);
 
-    // ---- per-digit tile counts, wave offsets and the tile's digit starts -------------
+    // ---- per-digit tile counts (published at once) and wave offsets ------------------
+    const uint32_t st0 = tile & ~(mst - 1);  // first tile of this tile's super-tile
+    uint32_t* mycnt = a.agg + (uint64_t)(tile & wmask) * sigma;
     for (uint32_t d = tid; d < sigma; d += NT) {
         uint32_t run = 0;
 #pragma unroll
@@ -273,6 +292,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             wh[w * SMAX + d] = run;
             run += c;
         }
+        st_agent(mycnt + d, run | epoch_bit(tile, wlog));
         cnt[d] = run;
         excl[d] = run;
     }
@@ -295,102 +315,51 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             ls[p] = (uint16_t)(wave * SEG + j * 64 + lane);
         }
     }
-    // Every load of the tile has returned once its value sits in LDS: from here on
-    // other tiles may reuse the tile's blocks.
     __syncthreads();
+    // registers are free again: issue the next tile's loads
+    load_tile(tile + gridDim.x);
 
     uint32_t* base = wh;                  // per-digit data reusing the wave counts
     uint32_t* nfw = wh + SMAX;
     uint2* dt = (uint2*)(wh + 2 * SMAX);  // (rank offset, table offset) per digit
 
-    // ---- publish counts and look back ------------------------------------------------
-    {
-        const uint64_t ep = (g >> wlog) + 1;                  // epoch of the 64-bit ring
-        const uint32_t mytag = ((tile >> wlog) + 1) & 3u;     // round-local epoch mod 4
-        uint64_t* myinc = a.ring + (g & wmask) * sigma;
-        uint16_t* myagg = a.agg + (uint64_t)(tile & wmask) * sigma;
-        for (uint32_t d = tid; d < sigma; d += NT) {
-            const uint32_t c = cnt[d];
-            uint64_t acc = 0;
-            if (tile == 0) {
-                st_agent(myinc + d, pack_status(c, kFlagInc, ep));
-                st_agent16(myagg + d, (uint16_t)(c | kAggHint | (mytag << 14)));
-            } else {
-                st_agent16(myagg + d, (uint16_t)(c | (mytag << 14)));
-                uint32_t k = tile;  // predecessors not yet summed: tiles 0 .. k-1
-                uint32_t spins = 0;
-                bool stalled = false;  // the nearest predecessor had nothing published yet
-                for (;;) {
-                    // read up to kLookbackWin predecessors at once; while waiting for
-                    // one that has not published, poll that one alone
-                    const uint32_t m = stalled ? 1u : min<uint32_t>(kLookbackWin, k);
-                    uint32_t w[kLookbackWin];
+    // ---- look back over the super-tile -----------------------------------------------
+    for (uint32_t d = tid; d < sigma; d += NT) {
+        // sum the counts of tiles st0 .. tile-1, up to kLookbackWin loads at once;
+        // while one has not published, poll that one alone
+        uint32_t acc = 0, k = tile, spins = 0;
+        bool stalled = false;
+        while (k > st0) {
+            const uint32_t m = stalled ? 1u : min<uint32_t>(kLookbackWin, k - st0);
+            uint32_t w[kLookbackWin];
 #pragma unroll
-                    for (int i = 0; i < kLookbackWin; i++) {
-                        if ((uint32_t)i < m)
-                            w[i] = ld_agent16(a.agg + (uint64_t)((k - 1 - i) & wmask) * sigma + d);
-                    }
-                    uint32_t used = 0;
-                    int state = 0;  // 0: all summed, 1: hint found, 2: not ready, 3: restart
+            for (int i = 0; i < kLookbackWin; i++)
+                if ((uint32_t)i < m)
+                    w[i] = ld_agent(a.agg + (uint64_t)((k - 1 - i) & wmask) * sigma + d);
+            uint32_t used = 0;
+            bool ready = true;
 #pragma unroll
-                    for (int i = 0; i < kLookbackWin; i++) {
-                        if ((uint32_t)i < m && state == 0) {
-                            const uint32_t want = (((k - 1 - i) >> wlog) + 1) & 3u;
-                            const uint32_t t = w[i] >> 14;
-                            if (t == want) {
-                                used = i + 1;
-                                if (w[i] & kAggHint) state = 1;
-                                else acc += w[i] & 0x1FFFu;
-                            } else if (t == ((want + 1) & 3u)) {
-                                state = 3;
-                            } else {
-                                state = 2;
-                            }
-                        }
-                    }
-                    if (state == 1) {
-                        // the nearest tile with an inclusive prefix: read it from the ring
-                        const uint64_t gk = a.seq_base + k - used, want = (gk >> wlog) + 1;
-                        const uint64_t* p = a.ring + (gk & wmask) * sigma + d;
-                        bool ok = false;
-                        for (;;) {
-                            const uint64_t s = ld_agent(p);
-                            if ((s >> 34) == want && ((s >> 32) & 3u) == kFlagInc) {
-                                acc += (uint32_t)s;
-                                ok = true;
-                                break;
-                            }
-                            if ((s >> 34) > want) break;  // overwritten: start over
-                            if (spin_give_up(++spins, a.err)) { ok = true; break; }
-                            spin_pause();
-                        }
-                        if (ok) break;
-                        acc = 0;
-                        k = tile;
-                        stalled = false;
-                        continue;
-                    }
-                    if (state == 3) {  // overwritten by a later tile: start over
-                        acc = 0;
-                        k = tile;
-                        stalled = false;
-                        continue;
-                    }
-                    k -= used;
-                    if (k == 0) break;  // never: tile 0 is always inclusive
-                    stalled = state == 2 && used == 0;
-                    if (state == 2) {
-                        if (spin_give_up(++spins, a.err)) break;
-                        spin_pause();
+            for (int i = 0; i < kLookbackWin; i++) {
+                if ((uint32_t)i < m && ready) {
+                    if ((w[i] & ~kCntMask) == epoch_bit(k - 1 - i, wlog)) {
+                        acc += w[i] & kCntMask;
+                        used = i + 1;
+                    } else {
+                        ready = false;
                     }
                 }
-                st_agent(myinc + d, pack_status(acc + c, kFlagInc, ep));
-                st_agent16(myagg + d, (uint16_t)(c | kAggHint | (mytag << 14)));
             }
-            base[d] = (uint32_t)acc;
+            k -= used;
+            stalled = !ready && used == 0;
+            if (!ready) {
+                if (spin_give_up(++spins, a.err)) break;
+                spin_pause();
+            }
         }
+        base[d] = a.stbase[(uint64_t)(tile >> a.st_log2) * sigma + d] + acc;
     }
     __syncthreads();
+    if (tid == 0) st_agent(a.done + (tile & wmask), tile + 1);
 
     if constexpr (OOP) {
         for (uint32_t d = tid; d < sigma; d += NT) dt[d].x = a.est[d] + base[d] - excl[d];
@@ -403,18 +372,51 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             if constexpr (VB != 0) a.Tv[pos] = lv[p];
         }
     } else {
-        // ---- block draws --------------------------------------------------------------
-        uint32_t fsum = 0;
+        // ---- block draws ----------------------------------------------------------------
+        // Request the block that takes each digit's first elements (drawn by an
+        // earlier tile) now; it is used after this tile's own draws are out.
+        uint32_t first = kEmpty;  // pi_new entry of that block, for digit tid
+        uint32_t fsum = 0, nsum = 0;
         for (uint32_t d = tid; d < sigma; d += NT) {
             const uint32_t bs = base[d], c = cnt[d], q0 = bs >> log2b;
             const uint32_t nfill = ((bs + c) >> log2b) - q0;
             const uint32_t nwrite = c ? ((bs + c - 1) >> log2b) - q0 + 1 : 0u;
+            const uint32_t L = a.S[d] + q0;
+            if (d == tid && c && q0 > 0 && L < a.npi) first = ld_agent(a.pi_new + L);
             nfw[d] = (nfill << 16) | nwrite;
             tbo[d] = nwrite;
             fsum += q0;
+            nsum += nfill;
         }
         for (uint32_t i = tid; i < E / 32; i += NT) fmask[i] = 0;
-        const uint32_t F = block_sum<NT>(fsum, tmp);  // draws made by earlier tiles
+        // F: draws made by earlier tiles; nfills: draws of this tile
+        fsum = wave_sum(fsum);
+        nsum = wave_sum(nsum);
+        if (lane == 0) {
+            tmp[wave] = fsum;
+            tmp[NT / 64 + wave] = nsum;
+        }
+        __syncthreads();
+        uint32_t F = 0, nfills = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; w++) {
+            F += tmp[w];
+            nfills += tmp[NT / 64 + w];
+        }
+        // request the pool entries of the draws, and the done words of the
+        // earlier tiles whose input blocks they are
+        uint32_t pv = 0;
+        if (tid < nfills) {
+            const uint32_t h = sigma + F + tid;
+            pv = h < a.npi ? a.pi_old[h] : a.npi;
+        }
+        uint32_t olo = 0, ohi = 0, dv = ~0u;
+        if (nfills) {
+            olo = (uint32_t)(((uint64_t)F << log2b) / E);
+            ohi = min<uint32_t>((uint32_t)((((uint64_t)(F + nfills) << log2b) - 1) / E) + 1, st0);
+            if (olo + tid < ohi) dv = ld_agent(a.done + ((olo + tid) & wmask));
+        }
+        __syncthreads();  // tmp is reused by the scan
         const uint32_t nent = block_excl_scan<NT>(tbo, sigma, tmp);
         // mark the slots whose element fills a block
         for (uint32_t d = tid; d < sigma; d += NT) {
@@ -427,12 +429,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
         }
         __syncthreads();
         for (uint32_t i = tid; i < E / 32; i += NT) fpref[i] = __popc(fmask[i]);
+        if (tid < nfills) pool[tid] = pv;
+        for (uint32_t i = tid + NT; i < nfills; i += NT) {  // more draws than threads: rare
+            const uint32_t h = sigma + F + i;
+            pool[i] = h < a.npi ? a.pi_old[h] : a.npi;
+        }
         __syncthreads();
         block_excl_scan<NT>(fpref, E / 32, tmp);
-        // Publish the tile's own draws first, for every digit, and only then wait for
-        // the blocks earlier tiles drew.  A wave runs its 64 digits in lock step, so
-        // a wait placed before the publications would hold all of them back and chain
-        // every tile to the publications of the one before it.
+        // publish the tile's draws for every digit
         for (uint32_t d = tid; d < sigma; d += NT) {
             const uint32_t bs = base[d], q0 = bs >> log2b;
             const uint32_t nfill = nfw[d] >> 16, nwrite = nfw[d] & 0xFFFFu, t0 = tbo[d];
@@ -441,49 +445,50 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
                 const uint32_t lr = ((q0 + i) << log2b) - 1 - bs;
                 const uint32_t s = ls[excl[d] + lr];
                 const uint32_t r = fpref[s >> 5] + __popc(fmask[s >> 5] & ((1u << (s & 31)) - 1u));
-                const uint32_t h = sigma + F + r, L = Sd + q0 + i;
-                uint32_t phys = 0;
-                if (h < a.npi && L < a.npi) {
-                    phys = a.pi_old[h];
+                const uint32_t L = Sd + q0 + i;
+                uint32_t phys = r < nfills ? pool[r] : a.npi;
+                if (phys < a.npi && L < a.npi) {
                     st_agent(a.pi_new + L, phys);
-                    __hip_atomic_fetch_max(a.opened + d, ((uint64_t)(q0 + i) << 32) | phys,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else {
                     raise_error(a.err, kErrBounds);
+                    phys = 0;
                 }
                 if (i < nwrite) tphys[t0 + i] = phys;
             }
         }
+        // The drawn blocks are input blocks sigma + F .. sigma + F + nfills - 1.  Those
+        // of this super-tile were loaded before their tiles' counts, which the
+        // look-back read; for earlier tiles wait until they are done.
+        for (uint32_t o = olo + tid; o < ohi; o += NT) {
+            const uint32_t* w = a.done + (o & wmask);
+            uint32_t v = o == olo + tid ? dv : ld_agent(w), spins = 0;
+            while (v <= o) {
+                if (spin_give_up(++spins, a.err)) break;
+                spin_pause();
+                v = ld_agent(w);
+            }
+        }
+        // the block of each digit's first elements
         for (uint32_t d = tid; d < sigma; d += NT) {
-            const uint32_t bs = base[d], c = cnt[d], q0 = bs >> log2b, t0 = tbo[d];
-            const uint32_t Sd = a.S[d];
+            const uint32_t bs = base[d], c = cnt[d], q0 = bs >> log2b;
             if (c) {
-                uint32_t phys;
+                uint32_t phys = d == tid ? first : kEmpty;
                 if (q0 == 0) {
                     phys = a.pi_old[d];
-                } else if (Sd + q0 >= a.npi) {
+                } else if (a.S[d] + q0 >= a.npi) {
                     raise_error(a.err, kErrBounds);
                     phys = 0;
                 } else {
-                    // drawn by an earlier tile.  Usually it is the bucket's latest draw,
-                    // read from one coalesced word per bucket; otherwise wait for its
-                    // entry of pi'.
-                    const uint64_t o = ld_agent(a.opened + d);
-                    if ((uint32_t)(o >> 32) == q0) {
-                        phys = (uint32_t)o;
-                    } else {
-                        uint32_t spins = 0;
-                        for (;;) {
-                            phys = ld_agent(a.pi_new + Sd + q0);
-                            if (phys != kEmpty) break;
-                            if (spin_give_up(++spins, a.err)) { phys = 0; break; }
-                            spin_pause();
-                        }
+                    uint32_t spins = 0;
+                    while (phys == kEmpty) {
+                        if (spin_give_up(++spins, a.err)) { phys = 0; break; }
+                        spin_pause();
+                        phys = ld_agent(a.pi_new + a.S[d] + q0);
                     }
                 }
-                tphys[t0] = phys;
+                tphys[tbo[d]] = phys;
             }
-            dt[d] = make_uint2(bs - excl[d], t0 - q0);
+            dt[d] = make_uint2(bs - excl[d], tbo[d] - q0);
         }
         __syncthreads();
         for (uint32_t e = tid; e < nent; e += NT) {

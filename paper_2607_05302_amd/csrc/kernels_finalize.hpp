@@ -29,7 +29,7 @@
 
 namespace rs {
 
-constexpr uint32_t kFinJob = 2048;      // nodes per job of F1
+constexpr uint32_t kFinJob = 1024;      // nodes per job of F1
 constexpr uint32_t kFinCols = 256;      // columns of a block moved by one F1 workgroup
 constexpr uint32_t kFinDepth = 8;       // loads in flight per thread in F1
 constexpr uint32_t kScanTile = 4096;    // elements per workgroup of the device scan

@@ -1,0 +1,117 @@
+// Digit starts of super-tiles: the count of each digit before every group of
+// 2^st_log2 tiles of a round's input.  A tile of the round kernel then looks
+// back only over the earlier tiles of its own super-tile, so no chain of
+// look-backs runs across the whole launch.
+//
+// Slots follow the round kernel: slot s of the input is element (s mod b) of
+// logical block sigma + floor(s / b), used when (s mod b) < blen of that block
+// (Radsort), or element s of the array (out-of-place).  Super-tile u covers
+// slots [u * 2^sts_log2, (u + 1) * 2^sts_log2).
+#pragma once
+
+#include "common.hpp"
+
+namespace rs {
+
+constexpr int kHistCopies = 16384;  // LDS words of per-wave digit counts per workgroup
+constexpr int kScanRows = 64;       // super-tiles per chunk of the column scan
+
+// cnt[u * sigma + d] = elements of super-tile u with digit d (for every u of the
+// grid; super-tiles past the input write zeros), and csum[c * sigma + d] += the
+// same for chunk c = floor(u / kScanRows) (csum zero on entry).
+template <int KB, bool OOP, int NT>
+__global__ __launch_bounds__(NT) void k_supertile_counts(
+    const typename UInt<KB>::T* __restrict__ Ak, const typename UInt<KB>::T* __restrict__ Tk,
+    const uint32_t* __restrict__ pi, const uint32_t* __restrict__ blen,
+    const uint32_t* __restrict__ f_in_p, uint64_t n, uint32_t shift, uint32_t bits,
+    uint32_t log2b, uint32_t npi, uint32_t sts_log2, uint32_t* __restrict__ cnt,
+    uint32_t* __restrict__ csum, uint32_t* err)
+{
+    using K = typename UInt<KB>::T;
+    constexpr int NW = NT / 64;
+    constexpr int U = 16;  // loads in flight per lane
+    __shared__ uint32_t h[kHistCopies];
+    const uint32_t sigma = 1u << bits, dmask = sigma - 1, two_sigma = 2 * sigma;
+    const uint32_t copies = min<uint32_t>(NW, kHistCopies / sigma);
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t* mine = h + (wave % copies) * sigma;
+    for (uint32_t i = tid; i < copies * sigma; i += NT) h[i] = 0;
+    __syncthreads();
+
+    const uint64_t s0 = (uint64_t)blockIdx.x << sts_log2, span = 1ull << sts_log2;
+    if constexpr (OOP) {
+        const uint64_t s1 = min<uint64_t>(n, s0 + span);
+        for (uint64_t c = s0 + (uint64_t)wave * 64 * U; c < s1; c += (uint64_t)NW * 64 * U) {
+            K x[U];
+#pragma unroll
+            for (int j = 0; j < U; j++) {
+                const uint64_t i = c + j * 64 + lane;
+                x[j] = i < s1 ? Ak[i] : (K)0;
+            }
+#pragma unroll
+            for (int j = 0; j < U; j++)
+                if (c + j * 64 + lane < s1) atomicAdd(mine + ((uint32_t)(x[j] >> shift) & dmask), 1u);
+        }
+    } else {
+        const uint32_t b = 1u << log2b;
+        const uint32_t f_in = max(sigma, min(*f_in_p, npi));
+        const uint32_t nblk = (uint32_t)(span >> log2b);
+        const uint32_t L0 = sigma + (uint32_t)(s0 >> log2b);
+        // each wave walks whole blocks; a block is read in chunks of 64 * U slots
+        for (uint32_t i = wave; i < nblk; i += NW) {
+            const uint32_t L = L0 + i;
+            if (L >= f_in) break;
+            const uint32_t phys = pi[L];
+            const uint32_t len = min(blen[L], b);
+            if (phys >= npi) {  // never for a consistent state
+                if (lane == 0) raise_error(err, kErrBounds);
+                continue;
+            }
+            const K* kp = blockat(Ak, Tk, phys, two_sigma, log2b);
+            for (uint32_t c = 0; c < len; c += 64 * U) {
+                K x[U];
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    const uint32_t o = c + j * 64 + lane;
+                    x[j] = o < len ? kp[o] : (K)0;
+                }
+#pragma unroll
+                for (int j = 0; j < U; j++)
+                    if (c + j * 64 + lane < len)
+                        atomicAdd(mine + ((uint32_t)(x[j] >> shift) & dmask), 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = tid; d < sigma; d += NT) {
+        uint32_t s = 0;
+        for (uint32_t c = 0; c < copies; c++) s += h[c * sigma + d];
+        cnt[(uint64_t)blockIdx.x * sigma + d] = s;
+        if (s) atomicAdd(csum + (uint64_t)(blockIdx.x / kScanRows) * sigma + d, s);
+    }
+}
+
+// In place, for every digit d: cnt[u * sigma + d] becomes sum_{u' < u} cnt[u' * sigma + d].
+// Workgroup c takes the rows of chunk c: it adds up the sums of the earlier
+// chunks, then runs through its own rows.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_column_scan(uint32_t* cnt, const uint32_t* csum,
+                                                    uint32_t rows, uint32_t sigma)
+{
+    const uint32_t c = blockIdx.x, r0 = c * kScanRows, r1 = min(rows, r0 + kScanRows);
+    for (uint32_t d = threadIdx.x; d < sigma; d += NT) {
+        uint32_t run = 0;
+        for (uint32_t i = 0; i < c; i++) run += csum[(uint64_t)i * sigma + d];
+        uint32_t x[kScanRows];
+#pragma unroll
+        for (int i = 0; i < kScanRows; i++)
+            x[i] = r0 + i < r1 ? cnt[(uint64_t)(r0 + i) * sigma + d] : 0u;
+#pragma unroll
+        for (int i = 0; i < kScanRows; i++) {
+            if (r0 + i < r1) cnt[(uint64_t)(r0 + i) * sigma + d] = run;
+            run += x[i];
+        }
+    }
+}
+
+}  // namespace rs

@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "kernels_state.hpp"
 #include "kernel_round.hpp"
+#include "kernels_prefix.hpp"
 #include "kernels_finalize.hpp"
 #include "kernels_finalize_seq.hpp"
 
@@ -34,7 +35,8 @@ radsort_stats g_stats{};
         }                                            \
     } while (0)
 
-constexpr uint32_t kRingWords = 1u << 19;  // look-back ring: 2^ring_log2 * sigma status words
+constexpr uint32_t kRingWords = 1u << 19;  // look-back ring: 2^ring_log2 * sigma count words
+constexpr uint32_t kSuperLog2 = 4;         // tiles per super-tile: 16, or enough to hold a block
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -45,9 +47,13 @@ int ilog2(uint64_t x)
     return r;
 }
 
-// Tile shape per element size: E = 64 * WAVES * ITEMS slots per workgroup.
-template <int KB, int VB> struct TileCfg {
-    static constexpr int WAVES = 4;
+// Tile shape per record size and digit width: E = 64 * WAVES * ITEMS slots per
+// workgroup.  Bigger tiles mean fewer look-back steps and block requests per
+// element; the staged tile and the per-wave digit counts must fit in LDS (one
+// workgroup of up to 110 KB per CU), and the next tile's records, held in
+// registers while the current one is processed, must fit the register file.
+template <int KB, int VB, bool WIDE> struct TileCfg {
+    static constexpr int WAVES = WIDE ? 4 : 8;
     static constexpr int ITEMS = (KB + VB >= 12) ? 8 : 16;
     static constexpr int E = 64 * WAVES * ITEMS;
 };
@@ -57,23 +63,31 @@ struct Geo {
     uint32_t kb = 0, vb = 0, bits = 0, sigma = 0, nt = 0, b = 0, log2b = 0;
     uint64_t nb = 0;
     uint32_t npi = 0, E = 0, tiles = 0, ring_w = 0, ring_log2 = 0;
+    uint32_t st_log2 = 0;                 // tiles per super-tile: 2^st_log2
+    uint32_t supers = 0, oop_supers = 0;  // super-tiles of a Radsort / out-of-place round
 };
 
 // Workspace regions (byte offsets), each 256-byte aligned.
 struct Layout {
-    uint64_t Tk, Tv, pi0, pi1, blen, opened, hist, S, Pidx, Plen, f, est, ctr, agg, ring, fin,
-        alt_k, alt_v;
+    uint64_t Tk, Tv, pi0, pi1, blen, opened, hist, S, Pidx, Plen, f, est, ctr, ring, agg, done,
+        csum, stcnt, fin, alt_k, alt_v;
     uint64_t ring_bytes, fin_bytes, total;
 };
 
-uint32_t tile_elems(uint32_t kb, uint32_t vb)
+template <bool WIDE> uint32_t tile_elems_t(uint32_t kb, uint32_t vb)
 {
-    if (kb == 4 && vb == 0) return TileCfg<4, 0>::E;
-    if (kb == 4 && vb == 4) return TileCfg<4, 4>::E;
-    if (kb == 4 && vb == 8) return TileCfg<4, 8>::E;
-    if (kb == 8 && vb == 0) return TileCfg<8, 0>::E;
-    if (kb == 8 && vb == 4) return TileCfg<8, 4>::E;
-    return TileCfg<8, 8>::E;
+    if (kb == 4 && vb == 0) return TileCfg<4, 0, WIDE>::E;
+    if (kb == 4 && vb == 4) return TileCfg<4, 4, WIDE>::E;
+    if (kb == 4 && vb == 8) return TileCfg<4, 8, WIDE>::E;
+    if (kb == 8 && vb == 0) return TileCfg<8, 0, WIDE>::E;
+    if (kb == 8 && vb == 4) return TileCfg<8, 4, WIDE>::E;
+    return TileCfg<8, 8, WIDE>::E;
+}
+
+// digits of more than 8 bits take the wide tile (per-wave counts of 2^11 digits)
+uint32_t tile_elems(uint32_t kb, uint32_t vb, uint32_t bits)
+{
+    return bits > 8 ? tile_elems_t<true>(kb, vb) : tile_elems_t<false>(kb, vb);
 }
 
 int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bits,
@@ -99,12 +113,17 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     // pi entries are 32-bit with the top bit free; finalize scans at most 4096^2 entries
     if (npi >= (uint64_t)kScanTile * kScanTile) return RADSORT_E_UNSUPPORTED;
     g.npi = (uint32_t)npi;
-    g.E = tile_elems(g.kb, g.vb);
+    g.E = tile_elems(g.kb, g.vb, g.bits);
     // input slots of a round: at most (floor(n/b) + sigma) blocks of b
     uint64_t slots = (g.nb + g.sigma) << g.log2b;
     g.tiles = (uint32_t)((slots + g.E - 1) / g.E);
     g.ring_w = std::max<uint32_t>(256u, kRingWords / g.sigma);  // powers of two
     g.ring_log2 = ilog2(g.ring_w);
+    g.st_log2 = std::max<uint32_t>(kSuperLog2, g.log2b > (uint32_t)ilog2(g.E)
+                                                   ? g.log2b - (uint32_t)ilog2(g.E) : 0u);
+    g.supers = (g.tiles + (1u << g.st_log2) - 1) >> g.st_log2;
+    const uint64_t oop_tiles = (n + g.E - 1) / g.E;
+    g.oop_supers = (uint32_t)((oop_tiles + (1u << g.st_log2) - 1) >> g.st_log2);
     return RADSORT_OK;
 }
 
@@ -139,20 +158,31 @@ Layout make_layout(const Geo& g, bool oop)
     L.f = take(4 * (nt + 1));
     L.est = take(4 * nt * sig);
     L.ctr = take(4 * (nt + 8));
-    L.agg = take(2ull * g.ring_w * sig);
-    L.ring_bytes = 8ull * g.ring_w * sig;
+    // the look-back ring (count words, done words) and the chunk sums of the
+    // super-tile scan, zeroed before each round; then the super-tile digit starts.
+    // Finalize reuses all of it.
+    const uint64_t supers = oop ? g.oop_supers : g.supers;
+    const uint64_t agg_bytes = 4ull * g.ring_w * sig;
+    const uint64_t done_bytes = align_up(4ull * g.ring_w, 256);
+    const uint64_t csum_bytes = align_up(4ull * ((supers + kScanRows - 1) / kScanRows) * sig, 256);
+    L.ring_bytes = agg_bytes + done_bytes + csum_bytes;
+    const uint64_t st_bytes = align_up(4ull * supers * sig, 256);
     L.fin_bytes = oop ? 0 : finalize_bytes(g);
-    L.ring = take(std::max(L.ring_bytes, L.fin_bytes));  // finalize reuses the ring
+    L.ring = take(std::max(L.ring_bytes + st_bytes, L.fin_bytes));
+    L.agg = L.ring;
+    L.done = L.ring + agg_bytes;
+    L.csum = L.done + done_bytes;
+    L.stcnt = L.ring + L.ring_bytes;
     L.fin = L.ring;
     L.total = o;
     return L;
 }
 
 // HIP events recorded on the call's stream around each phase (RADSORT_F_TIMING).
-enum Mark { kStart, kSetupEnd, kRoundBegin, kRoundEnd, kFixupEnd, kFinBegin, kFinEnd };
+enum Mark { kStart, kSetupEnd, kCountBegin, kRoundBegin, kRoundEnd, kFixupEnd, kFinBegin, kFinEnd };
 
 struct Timer {
-    static constexpr int kMax = 8 + 3 * RADSORT_MAX_ROUNDS;
+    static constexpr int kMax = 8 + 4 * RADSORT_MAX_ROUNDS;
     hipEvent_t ev[kMax];
     int tag[kMax], round[kMax];
     int count = 0;
@@ -194,14 +224,15 @@ struct Timer {
         };
         st.timed = 1;
         st.setup_ms = st.fixup_ms = st.finalize_ms = 0;
-        for (int r = 0; r < RADSORT_MAX_ROUNDS; r++) st.round_ms[r] = 0;
+        for (int r = 0; r < RADSORT_MAX_ROUNDS; r++) st.round_ms[r] = st.count_ms[r] = 0;
         st.total_ms = ms(0, count - 1);
         for (int i = 1; i < count; i++) {
             const float d = ms(i - 1, i);
             switch (tag[i]) {
             case kSetupEnd: st.setup_ms += d; break;
             case kRoundEnd: st.round_ms[round[i] % RADSORT_MAX_ROUNDS] += d; break;
-            case kRoundBegin:
+            case kRoundBegin: st.count_ms[round[i] % RADSORT_MAX_ROUNDS] += d; break;
+            case kCountBegin:
             case kFixupEnd: st.fixup_ms += d; break;
             case kFinEnd: st.finalize_ms += d; break;
             default: st.setup_ms += d; break;  // gaps before a finalize
@@ -229,7 +260,6 @@ struct radsort_state {
     void* keys = nullptr;
     void* vals = nullptr;
     uint32_t rounds_done = 0;  // rounds since setup
-    uint64_t seq = 0;          // look-back ring sequence of the next round's tile 0
     int cur = 0;               // which pi buffer holds pi
     bool is_setup = false;
 
@@ -301,17 +331,39 @@ int launch_persistent(const void* kern, uint32_t tiles, uint32_t threads, Args& 
     return RADSORT_OK;
 }
 
+// Digit counts of every super-tile of a round's input, then their column scan:
+// stcnt[u][d] = elements with digit d before super-tile u.
+template <int KB, bool OOP>
+void launch_super_counts(const Geo& g, const typename UInt<KB>::T* Ak,
+                         const typename UInt<KB>::T* Tk, const uint32_t* pi,
+                         const uint32_t* blen, const uint32_t* f_in, uint32_t shift,
+                         uint32_t* stcnt, uint32_t* csum, uint32_t* err, hipStream_t s)
+{
+    const uint32_t supers = OOP ? g.oop_supers : g.supers;
+    if (!supers) return;
+    const uint32_t sts_log2 = g.st_log2 + (uint32_t)ilog2(g.E);
+    hipLaunchKernelGGL((k_supertile_counts<KB, OOP, 1024>), dim3(supers), dim3(1024), 0, s, Ak,
+                       Tk, pi, blen, f_in, g.n, shift, g.bits, g.log2b, g.npi, sts_log2, stcnt,
+                       csum, err);
+    hipLaunchKernelGGL(k_column_scan<256>, dim3((supers + kScanRows - 1) / kScanRows), dim3(256),
+                       0, s, stcnt, csum, supers, g.sigma);
+}
+
 template <int KB, int VB, bool OOP>
 int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s)
 {
-    constexpr int W = TileCfg<KB, VB>::WAVES, I = TileCfg<KB, VB>::ITEMS;
+    using N = TileCfg<KB, VB, false>;
+    using Wd = TileCfg<KB, VB, true>;
     const uint32_t tiles = OOP ? (uint32_t)((g.n + g.E - 1) / g.E) : g.tiles;
     if (tiles == 0) return RADSORT_OK;
-    const void* kern;
-    if (g.bits == 8) kern = (const void*)&k_round<KB, VB, OOP, 8, 256, W, I>;
-    else if (g.bits <= 8) kern = (const void*)&k_round<KB, VB, OOP, 0, 256, W, I>;
-    else kern = (const void*)&k_round<KB, VB, OOP, 0, 2048, W, I>;
-    return launch_persistent(kern, tiles, 64 * W, a, s);
+    if (g.bits == 8)
+        return launch_persistent((const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS>,
+                                 tiles, 64 * N::WAVES, a, s);
+    if (g.bits < 8)
+        return launch_persistent((const void*)&k_round<KB, VB, OOP, 0, 256, N::WAVES, N::ITEMS>,
+                                 tiles, 64 * N::WAVES, a, s);
+    return launch_persistent((const void*)&k_round<KB, VB, OOP, 0, 2048, Wd::WAVES, Wd::ITEMS>,
+                             tiles, 64 * Wd::WAVES, a, s);
 }
 
 template <int KB, int VB> struct Ops {
@@ -325,7 +377,6 @@ template <int KB, int VB> struct Ops {
         launch_histograms<KB>(st->keys, g, st->u32(st->L.hist), s);
         launch_plan(g, st->u32(st->L.hist), st->plan(), s);
         launch_fill(st->u32(st->L.ctr), g.nt + 8, 0, s);
-        launch_fill((uint32_t*)(st->ws + st->L.ring), st->L.ring_bytes / 4, 0, s);
         uint64_t work = std::max<uint64_t>(g.npi, g.n & (g.b - 1));
         uint32_t grid = (uint32_t)std::min<uint64_t>((work + 255) / 256, 4096);
         hipLaunchKernelGGL((k_setup<KB, VB>), dim3(grid), dim3(256), 0, s, (K*)st->keys,
@@ -335,7 +386,6 @@ template <int KB, int VB> struct Ops {
         g_timer.mark(kSetupEnd, 0, s);
         st->cur = 0;
         st->rounds_done = 0;
-        st->seq = 0;
         st->is_setup = true;
         return RADSORT_OK;
     }
@@ -356,16 +406,21 @@ template <int KB, int VB> struct Ops {
         a.f_in = st->u32(st->L.f) + r;
         a.S = st->u32(st->L.S) + r * g.sigma;
         a.opened = (uint64_t*)(st->ws + st->L.opened);
-        a.ring = (uint64_t*)(st->ws + st->L.ring);
-        a.agg = (uint16_t*)(st->ws + st->L.agg);
+        a.agg = (uint32_t*)(st->ws + st->L.agg);
+        a.done = (uint32_t*)(st->ws + st->L.done);
         a.err = st->err();
-        a.seq_base = st->seq;
         a.shift = g.bits * (g.nt - 1 - t);
         a.bits = g.bits;
         a.log2b = g.log2b;
         a.npi = g.npi;
         a.ring_log2 = g.ring_log2;
-        launch_fill((uint32_t*)a.agg, (uint64_t)g.ring_w * g.sigma / 2, 0, s);
+        a.st_log2 = g.st_log2;
+        uint32_t* stcnt = (uint32_t*)(st->ws + st->L.stcnt);
+        a.stbase = stcnt;
+        launch_fill(a.agg, st->L.ring_bytes / 4, 0, s);
+        g_timer.mark(kCountBegin, r, s);
+        launch_super_counts<KB, false>(g, a.Ak, a.Tk, a.pi_old, a.blen, a.f_in, a.shift, stcnt,
+                                       st->u32(st->L.csum), a.err, s);
         g_timer.mark(kRoundBegin, r, s);
         int rc = launch_round_t<KB, VB, false>(g, a, s);
         if (rc) return rc;
@@ -379,7 +434,6 @@ template <int KB, int VB> struct Ops {
         g_timer.mark(kFixupEnd, r, s);
         st->cur ^= 1;
         st->rounds_done++;
-        st->seq += g.tiles;
         return RADSORT_OK;
     }
 
@@ -448,11 +502,9 @@ template <int KB, int VB> struct Ops {
         launch_plan(g, hist, p, s);
         uint32_t* ctr = (uint32_t*)(ws + L.ctr);
         launch_fill(ctr, g.nt + 8, 0, s);
-        launch_fill((uint32_t*)(ws + L.ring), L.ring_bytes / 4, 0, s);
         g_timer.mark(kSetupEnd, 0, s);
         K* bk[2] = {(K*)keys, (K*)(ws + L.alt_k)};
         V* bv[2] = {(V*)vals, (V*)(ws + L.alt_v)};
-        const uint32_t tiles = (uint32_t)((g.n + g.E - 1) / g.E);
         for (uint32_t r = 0; r < g.nt; r++) {
             const uint32_t t = g.nt - 1 - r, from = r & 1;
             TileArgs<KB, VB> a{};
@@ -462,15 +514,20 @@ template <int KB, int VB> struct Ops {
             a.Tv = bv[from ^ 1];
             a.est = p.est + r * g.sigma;
             a.n = g.n;
-            a.ring = (uint64_t*)(ws + L.ring);
-            a.agg = (uint16_t*)(ws + L.agg);
+            a.agg = (uint32_t*)(ws + L.agg);
+            a.done = (uint32_t*)(ws + L.done);
             a.err = ctr + g.nt;
-            a.seq_base = (uint64_t)r * tiles;
             a.shift = g.bits * (g.nt - 1 - t);
             a.bits = g.bits;
             a.log2b = g.log2b;
             a.ring_log2 = g.ring_log2;
-            launch_fill((uint32_t*)a.agg, (uint64_t)g.ring_w * g.sigma / 2, 0, s);
+            a.st_log2 = g.st_log2;
+            uint32_t* stcnt = (uint32_t*)(ws + L.stcnt);
+            a.stbase = stcnt;
+            launch_fill(a.agg, L.ring_bytes / 4, 0, s);
+            g_timer.mark(kCountBegin, r, s);
+            launch_super_counts<KB, true>(g, a.Ak, (const K*)nullptr, nullptr, nullptr, nullptr,
+                                          a.shift, stcnt, (uint32_t*)(ws + L.csum), a.err, s);
             g_timer.mark(kRoundBegin, r, s);
             int rc = launch_round_t<KB, VB, true>(g, a, s);
             if (rc) return rc;
