@@ -3,10 +3,12 @@
 
 Workload: n = 2^28 uint32 keys, uniform over [0, 2^32) (splitmix64, seed
 0x5EED0002), uint32 payload = original index, 8-bit digits (sigma = 256, n_t = 4),
-block size b = 1024.  One step is one complete Radsort of that array on the GPU:
-digit histograms, setup, four sort rounds with their fixups, and finalize.  The
-input is restored from a pristine device copy before every step; the restore
-lies outside the HIP events that time the step.
+block size b = 2048 (the fastest b whose workspace stays under 1% of the input;
+--block picks another).  One step is one complete Radsort of that array on the
+GPU: digit histograms, setup, four sort rounds (each a super-tile counting pass
+and the round kernel) with their fixups, and finalize.  The input is restored
+from a pristine device copy before every step; the restore lies outside the HIP
+events that time the step.
 
 Printed: one JSON line with keys/s (value), the per-round roofline of the
 sort-round kernel (algorithmic bytes 2 n (s_k + s_v) per launch over its event
@@ -43,19 +45,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(n, elem_bytes):
+def measured_traffic(n, elem_bytes, b):
     """HBM bytes per sort-round launch from the committed counter runs, if they
-    were taken on the current kernel source; else None."""
+    were taken on the current kernel source and workload; else None."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("n") != n or t.get("elem_bytes") != elem_bytes:
+    if (t.get("kernel_sha") != kernel_sha() or t.get("n") != n
+            or t.get("elem_bytes") != elem_bytes or t.get("block_elems") != b):
         return None
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(keys_np, target_s):
+def cpu_baseline(keys_np, target_s, b):
     """The sequential C oracle on a prefix of the same input (1 host thread)."""
     import numpy as np
 
@@ -64,17 +67,17 @@ def cpu_baseline(keys_np, target_s):
     oracle.load()
     m = 1 << 20
     t = time.perf_counter()
-    oracle.radsort(keys_np[:m], np.arange(m, dtype=np.uint32), 256, 4, 1024)
+    oracle.radsort(keys_np[:m], np.arange(m, dtype=np.uint32), 256, 4, b)
     per_key = (time.perf_counter() - t) / m
     m = int(min(len(keys_np), max(1 << 20, target_s / per_key)))
     m = 1 << (m.bit_length() - 1)  # a power of two
     vals = np.arange(m, dtype=np.uint32)
     t = time.perf_counter()
-    oracle.radsort(keys_np[:m], vals, 256, 4, 1024)
+    oracle.radsort(keys_np[:m], vals, 256, 4, b)
     dt = time.perf_counter() - t
     return {"value": m / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": f"first {m} of the {len(keys_np)} keys (2^{m.bit_length() - 1}), "
-                      f"uint32 keys + uint32 index payload, b=1024, 8-bit digits, sequential "
+                      f"uint32 keys + uint32 index payload, b={b}, 8-bit digits, sequential "
                       f"C oracle (Alg. 2-7), {dt:.1f} s"}
 
 
@@ -84,7 +87,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--block", type=int, default=1024)
+    ap.add_argument("--block", type=int, default=2048)
     ap.add_argument("--no-oop", action="store_true", help="skip the out-of-place baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -192,7 +195,7 @@ def main():
     per_round = float(np.mean(round_ms))
     alg_bytes = 2 * n * (kb + vb)  # n reads + n writes of (key, payload) per round
     achieved = alg_bytes / (per_round / 1e3) / 1e9
-    traffic = measured_traffic(n, kb + vb)
+    traffic = measured_traffic(n, kb + vb, b)
     out = {
         "metric": METRIC,
         "value": n / (mean_ms / 1e3),
@@ -239,7 +242,7 @@ def main():
         out["extra_bytes_vs_oop"] = ws_bytes / oop_bytes
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_seconds, b)
     print(json.dumps(out), flush=True)
 
 

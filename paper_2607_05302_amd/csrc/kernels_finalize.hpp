@@ -31,7 +31,7 @@ namespace rs {
 
 constexpr uint32_t kFinJob = 1024;      // nodes per job of F1
 constexpr uint32_t kFinCols = 256;      // columns of a block moved by one F1 workgroup
-constexpr uint32_t kFinDepth = 8;       // loads in flight per thread in F1
+constexpr uint32_t kFinDepth = 16;      // loads in flight per thread in F1
 constexpr uint32_t kScanTile = 4096;    // elements per workgroup of the device scan
 constexpr uint32_t kGarbage = 0x80000000u;
 
@@ -289,10 +289,14 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
     const uint32_t col = blockIdx.y * kFinCols + threadIdx.x;
     const bool active = col < b;
     const uint32_t log2b = a.log2b;
-    uint32_t h[2];
-    job_heads(f.ord, rank, clen, j, M, a.npi, h[0], h[1]);
     const K* tk = (const K*)f.temps;
     const V* tv = (const V*)(f.temps + 2ull * ((a.npi + kFinJob - 1) / kFinJob) * b * KB);
+    // the job's part of the order array, and the whole cycle of a piece that
+    // crosses the job's start or end is read from global memory
+    __shared__ uint32_t sord[kFinJob];
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += kFinCols) sord[i - i0] = f.ord[i];
+    __syncthreads();
+    auto ord_at = [&](uint32_t i) { return i >= i0 && i < i1 ? sord[i - i0] : f.ord[i]; };
 
     // node ids come from the order array; an id outside [0, n_pi) is clamped to a
     // T block (only possible for a corrupt state, which also raises an error)
@@ -302,7 +306,7 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
 
     uint32_t i = i0;
     while (i < i1) {
-        const uint32_t p = f.ord[i] & ~kGarbage;
+        const uint32_t p = sord[i - i0] & ~kGarbage;
         if (p >= a.npi) {  // never for a consistent order array
             if (threadIdx.x == 0) raise_error(a.err, kErrBounds);
             return;
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
         // the head's content: from a register (whole cycle) or a saved block
         K hk{};
         V hv{};
-        const uint32_t head = f.ord[i];
+        const uint32_t head = sord[i - i0];
         const bool head_garbage = head & kGarbage;
         if (active && !head_garbage) {
             if (whole) {
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
 #pragma unroll
             for (uint32_t u = 0; u < kFinDepth; u++) {
                 if (u < cnt) {
-                    src[u] = f.ord[cb + x - 1 - u];
+                    src[u] = ord_at(cb + x - 1 - u);
                     if (active && !(src[u] & kGarbage)) {
                         bk[u] = *addr_k(src[u] & ~kGarbage);
                         if constexpr (VB != 0) bv[u] = *addr_v(src[u] & ~kGarbage);
@@ -351,7 +355,7 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
             for (uint32_t u = 0; u < kFinDepth; u++) {
                 if (u < cnt) {
                     const uint32_t rd = x - u;  // destination rank (mod L)
-                    const uint32_t dst = f.ord[cb + (rd == L ? 0 : rd)] & ~kGarbage;
+                    const uint32_t dst = ord_at(cb + (rd == L ? 0 : rd)) & ~kGarbage;
                     if (active && !(src[u] & kGarbage)) {
                         *addr_k(dst) = bk[u];
                         if constexpr (VB != 0) *addr_v(dst) = bv[u];
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
         // node(ra + 1 mod L) <- head
         {
             const uint32_t rd = ra + 1;
-            const uint32_t dst = f.ord[cb + (rd == L ? 0 : rd)] & ~kGarbage;
+            const uint32_t dst = ord_at(cb + (rd == L ? 0 : rd)) & ~kGarbage;
             if (active && !head_garbage) {
                 *addr_k(dst) = hk;
                 if constexpr (VB != 0) *addr_v(dst) = hv;
@@ -406,68 +410,73 @@ __device__ __forceinline__ void gap_before(const uint32_t* Pidx, const uint32_t*
 }
 
 // One chunk = CHUNK consecutive element positions of the A blocks (whole blocks,
-// or a part of one block when b > CHUNK), staged in LDS.
-template <int KB, int VB, int CHUNK>
-__global__ __launch_bounds__(256) void k_fin_compact(FinArgs<KB, VB> a, const uint32_t* gap,
-                                                     uint32_t* flags, uint32_t* ctr)
+// or a part of one block when b > CHUNK), held in registers.  The kernel is
+// persistent and launched cooperatively: workgroup w takes chunks w, w + G, ...,
+// and a chunk waits only for lower chunks to have loaded, so the waits end.
+template <int KB, int VB, int CHUNK, int NT>
+__global__ __launch_bounds__(NT) void k_fin_compact(FinArgs<KB, VB> a, const uint32_t* gap,
+                                                    uint32_t* flags, uint32_t chunks)
 {
     using K = typename UInt<KB>::T;
     using V = typename Payload<VB>::T;
     constexpr uint32_t MAXB = CHUNK / 64;
-    __shared__ K sk[CHUNK];
-    __shared__ V sv[VB ? CHUNK : 1];
+    constexpr int PER = CHUNK / NT;
     __shared__ uint32_t bG[MAXB], bL[MAXB];
-    __shared__ uint32_t s_chunk;
     const uint32_t tid = threadIdx.x, b = 1u << a.log2b, sigma = a.sigma, log2b = a.log2b;
     const uint64_t total = (a.n >> log2b) << log2b;  // positions of the full A blocks
-    if (tid == 0) s_chunk = add_agent(ctr, 1u);
-    __syncthreads();
-    const uint32_t c = s_chunk;
-    const uint64_t p0 = (uint64_t)c * CHUNK;
-    if (p0 >= total) return;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(CHUNK, total - p0);
-    const uint64_t j0 = p0 >> log2b;
-    const uint32_t nblk = (uint32_t)(((p0 + cnt - 1) >> log2b) - j0 + 1);
-    for (uint32_t i = tid; i < nblk; i += 256) {
-        uint32_t G, len;
-        gap_before(a.Pidx, a.Plen, gap, sigma, sigma + (uint32_t)(j0 + i), b, G, len);
-        bG[i] = G;
-        bL[i] = len;
-    }
-    __syncthreads();
-    if (bG[nblk - 1] == 0) {  // no gap before this chunk: it stays where it is
+    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        __syncthreads();  // the previous chunk is done with bG / bL
+        const uint64_t p0 = (uint64_t)c * CHUNK;
+        const uint32_t cnt = (uint32_t)min<uint64_t>(CHUNK, total - p0);
+        const uint64_t j0 = p0 >> log2b;
+        const uint32_t nblk = (uint32_t)(((p0 + cnt - 1) >> log2b) - j0 + 1);
+        for (uint32_t i = tid; i < nblk; i += NT) {
+            uint32_t G, len;
+            gap_before(a.Pidx, a.Plen, gap, sigma, sigma + (uint32_t)(j0 + i), b, G, len);
+            bG[i] = G;
+            bL[i] = len;
+        }
+        __syncthreads();
+        if (bG[nblk - 1] == 0) {  // no gap before this chunk: it stays where it is
+            if (tid == 0) st_agent(flags + c, 1u);
+            continue;
+        }
+        // load (elements beyond a block's length are never read)
+        K rk[PER];
+        V rv[PER];
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const uint32_t i = k * NT + tid;
+            const uint64_t pos = p0 + i;
+            const uint32_t jb = (uint32_t)((pos >> log2b) - j0), off = (uint32_t)pos & (b - 1);
+            const bool v = i < cnt && off < bL[jb];
+            rk[k] = v ? a.Ak[pos] : (K)0;
+            if constexpr (VB != 0) rv[k] = v ? a.Av[pos] : (V)0;
+        }
+        __builtin_amdgcn_s_waitcnt(0);  // every load of this thread has returned
+        __syncthreads();
         if (tid == 0) st_agent(flags + c, 1u);
-        return;
-    }
-    // load (elements beyond a block's length are never read)
-    for (uint32_t i = tid; i < cnt; i += 256) {
-        const uint64_t pos = p0 + i;
-        const uint32_t jb = (uint32_t)((pos >> log2b) - j0), off = (uint32_t)pos & (b - 1);
-        if (off < bL[jb]) {
-            sk[i] = a.Ak[pos];
-            if constexpr (VB != 0) sv[i] = a.Av[pos];
+        // wait for the chunks whose sources overlap the destination
+        const uint64_t dst0 = p0 - bG[0];
+        const uint32_t cfirst = (uint32_t)(dst0 / CHUNK);
+        for (uint32_t w = cfirst + tid; w < c; w += NT) {
+            uint32_t spins = 0;
+            while (ld_agent(flags + w) == 0u) {
+                if (spin_give_up(++spins, a.err)) break;
+                spin_pause();
+            }
         }
-    }
-    __syncthreads();
-    if (tid == 0) st_agent(flags + c, 1u);
-    // wait for the chunks whose sources overlap the destination
-    const uint64_t dst0 = p0 - bG[0];
-    const uint32_t cfirst = (uint32_t)(dst0 / CHUNK);
-    for (uint32_t w = cfirst + tid; w < c; w += 256) {
-        uint32_t spins = 0;
-        while (ld_agent(flags + w) == 0u) {
-            if (spin_give_up(++spins, a.err)) break;
-            spin_pause();
-        }
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < cnt; i += 256) {
-        const uint64_t pos = p0 + i;
-        const uint32_t jb = (uint32_t)((pos >> log2b) - j0), off = (uint32_t)pos & (b - 1);
-        if (off < bL[jb]) {
-            const uint64_t dst = pos - bG[jb];
-            a.Ak[dst] = sk[i];
-            if constexpr (VB != 0) a.Av[dst] = sv[i];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const uint32_t i = k * NT + tid;
+            const uint64_t pos = p0 + i;
+            const uint32_t jb = (uint32_t)((pos >> log2b) - j0), off = (uint32_t)pos & (b - 1);
+            if (i < cnt && off < bL[jb]) {
+                const uint64_t dst = pos - bG[jb];
+                a.Ak[dst] = rk[k];
+                if constexpr (VB != 0) a.Av[dst] = rv[k];
+            }
         }
     }
 }
@@ -504,8 +513,14 @@ inline void fin_scan(uint32_t* a, uint32_t count, uint32_t* sums, hipStream_t s)
     hipLaunchKernelGGL(k_scan_add, dim3(tiles), dim3(256), 0, s, a, count, sums);
 }
 
+// F2's chunk and its persistent launch: compact_grid workgroups of kCompactThreads,
+// at most as many as are resident at once (the caller gets it from the occupancy
+// of k_fin_compact<KB, VB, fin_chunk<KB, VB>(), kCompactThreads>).
+constexpr int kCompactThreads = 512;
+template <int KB, int VB> constexpr int fin_chunk() { return (KB + VB >= 12) ? 4096 : 8192; }
+
 template <int KB, int VB>
-int finalize_parallel(FinArgs<KB, VB>& a, hipStream_t s)
+int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
 {
     const uint32_t npi = a.npi, b = 1u << a.log2b;
     FinArrays f = fin_arrays(a.scratch, npi, a.n, a.spare_pi, a.spare_blen);
@@ -542,14 +557,18 @@ int finalize_parallel(FinArgs<KB, VB>& a, hipStream_t s)
     hipLaunchKernelGGL(k_fin_gaps, dim3(1), dim3(256), 4 * a.sigma, s, a.Pidx, a.Plen, a.sigma,
                        a.log2b, npi, gap);
     const uint64_t positions = (a.n >> a.log2b) << a.log2b;
-    constexpr int CHUNK = (KB + VB >= 12) ? kCompactMin : 2 * kCompactMin;
-    const uint32_t chunks = (uint32_t)((positions + CHUNK - 1) / CHUNK);
-    uint32_t* ctr = f.flags + (f.nflags - 1);  // counter after the flags
+    constexpr int CHUNK = fin_chunk<KB, VB>();
+    uint32_t chunks = (uint32_t)((positions + CHUNK - 1) / CHUNK);
     hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
                        dim3(256), 0, s, f.flags, f.nflags, 0u);
-    if (chunks)
-        hipLaunchKernelGGL((k_fin_compact<KB, VB, CHUNK>), dim3(chunks), dim3(256), 0, s, a, gap,
-                           f.flags, ctr);
+    if (chunks) {
+        const uint32_t grid = std::min(chunks, compact_grid);
+        if (!grid) return -1;
+        void* args[] = {(void*)&a, (void*)&gap, (void*)&f.flags, (void*)&chunks};
+        if (hipLaunchCooperativeKernel((const void*)&k_fin_compact<KB, VB, CHUNK, kCompactThreads>,
+                                       dim3(grid), dim3(kCompactThreads), args, 0, s) != hipSuccess)
+            return -1;
+    }
     // F3: the blocks in T
     hipLaunchKernelGGL((k_fin_tail<KB, VB>), dim3(a.sigma), dim3(256), 0, s, a, gap);
     return 0;

@@ -13,12 +13,14 @@
 
 namespace rs {
 
-constexpr int kHistCopies = 16384;  // LDS words of per-wave digit counts per workgroup
-constexpr int kScanRows = 64;       // super-tiles per chunk of the column scan
+constexpr int kHistCopies = 8192;  // LDS words of per-wave digit counts per workgroup
+constexpr int kScanRows = 64;      // super-tiles per chunk of the column scan
+constexpr int kMaxSuperBlocks = 2048;  // blocks of one super-tile held in LDS
 
 // cnt[u * sigma + d] = elements of super-tile u with digit d (for every u of the
 // grid; super-tiles past the input write zeros), and csum[c * sigma + d] += the
-// same for chunk c = floor(u / kScanRows) (csum zero on entry).
+// same for chunk c = floor(u / kScanRows) (csum zero on entry).  A super-tile
+// spans at most kMaxSuperBlocks blocks.
 template <int KB, bool OOP, int NT>
 __global__ __launch_bounds__(NT) void k_supertile_counts(
     const typename UInt<KB>::T* __restrict__ Ak, const typename UInt<KB>::T* __restrict__ Tk,
@@ -29,45 +31,61 @@ __global__ __launch_bounds__(NT) void k_supertile_counts(
 {
     using K = typename UInt<KB>::T;
     constexpr int NW = NT / 64;
-    constexpr int U = 16;  // loads in flight per lane
+    constexpr int U = 16;  // loads in flight per thread
     __shared__ uint32_t h[kHistCopies];
+    __shared__ uint32_t bphys[OOP ? 1 : kMaxSuperBlocks], blen_s[OOP ? 1 : kMaxSuperBlocks];
     const uint32_t sigma = 1u << bits, dmask = sigma - 1, two_sigma = 2 * sigma;
-    const uint32_t copies = min<uint32_t>(NW, kHistCopies / sigma);
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t copies = max(1u, min<uint32_t>(NW, kHistCopies / sigma));
+    const uint32_t tid = threadIdx.x, wave = tid >> 6;
     uint32_t* mine = h + (wave % copies) * sigma;
     for (uint32_t i = tid; i < copies * sigma; i += NT) h[i] = 0;
-    __syncthreads();
 
     const uint64_t s0 = (uint64_t)blockIdx.x << sts_log2, span = 1ull << sts_log2;
+    const uint32_t b = 1u << log2b;
+    uint64_t s1;
     if constexpr (OOP) {
-        const uint64_t s1 = min<uint64_t>(n, s0 + span);
-        for (uint64_t c = s0 + (uint64_t)wave * 64 * U; c < s1; c += (uint64_t)NW * 64 * U) {
-            K x[U];
-#pragma unroll
-            for (int j = 0; j < U; j++) {
-                const uint64_t i = c + j * 64 + lane;
-                x[j] = i < s1 ? Ak[i] : (K)0;
-            }
-#pragma unroll
-            for (int j = 0; j < U; j++)
-                if (c + j * 64 + lane < s1) atomicAdd(mine + ((uint32_t)(x[j] >> shift) & dmask), 1u);
-        }
+        s1 = min<uint64_t>(n, s0 + span);
     } else {
-        const uint32_t b = 1u << log2b;
         const uint32_t f_in = max(sigma, min(*f_in_p, npi));
         const uint32_t nblk = (uint32_t)(span >> log2b);
         const uint32_t L0 = sigma + (uint32_t)(s0 >> log2b);
-        // each wave walks whole blocks; a block is read in chunks of 64 * U slots
-        for (uint32_t i = wave; i < nblk; i += NW) {
+        for (uint32_t i = tid; i < nblk; i += NT) {
             const uint32_t L = L0 + i;
-            if (L >= f_in) break;
-            const uint32_t phys = pi[L];
-            const uint32_t len = min(blen[L], b);
-            if (phys >= npi) {  // never for a consistent state
-                if (lane == 0) raise_error(err, kErrBounds);
-                continue;
+            uint32_t phys = 0, len = 0;
+            if (L < f_in) {
+                phys = pi[L];
+                len = min(blen[L], b);
+                if (phys >= npi) {  // never for a consistent state
+                    raise_error(err, kErrBounds);
+                    phys = 0;
+                    len = 0;
+                }
             }
-            const K* kp = blockat(Ak, Tk, phys, two_sigma, log2b);
+            bphys[i] = phys;
+            blen_s[i] = len;
+        }
+        s1 = s0 + span;
+    }
+    __syncthreads();
+    if constexpr (OOP) {
+        for (uint64_t c = s0; c < s1; c += (uint64_t)NT * U) {
+            K x[U];
+#pragma unroll
+            for (int j = 0; j < U; j++) {
+                const uint64_t sl = c + (uint64_t)j * NT + tid;
+                x[j] = sl < s1 ? Ak[sl] : (K)0;
+            }
+#pragma unroll
+            for (int j = 0; j < U; j++)
+                if (c + (uint64_t)j * NT + tid < s1)
+                    atomicAdd(mine + ((uint32_t)(x[j] >> shift) & dmask), 1u);
+        }
+    } else {
+        // each wave reads whole blocks, U * 64 slots at a time
+        const uint32_t lane = tid & 63, nblk = (uint32_t)(span >> log2b);
+        for (uint32_t i = wave; i < nblk; i += NW) {
+            const uint32_t len = blen_s[i];
+            const K* kp = blockat(Ak, Tk, bphys[i], two_sigma, log2b);
             for (uint32_t c = 0; c < len; c += 64 * U) {
                 K x[U];
 #pragma unroll

@@ -16,28 +16,45 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t v)
 // Histograms of every key position in one pass over the keys (the first loop
 // of Alg. 1, taken for all positions up front as the paper's "generic" variant
 // does, Sec. 5).  hist[t * sigma + c] counts key(x, t) = c, t = 0 the most
-// significant digit.  hist must be zero on entry.  Dynamic LDS: nt * sigma words.
-template <int KB>
-__global__ __launch_bounds__(256) void k_histograms(const typename UInt<KB>::T* __restrict__ keys,
-                                                    uint64_t n, uint32_t bits, uint32_t nt,
-                                                    uint32_t* __restrict__ hist)
+// significant digit.  hist must be zero on entry.  Dynamic LDS: copies * nt *
+// sigma words, copies = the number of waves sharing a copy of the counts (each
+// wave adds into copy wave % copies).
+template <int KB, int NT>
+__global__ __launch_bounds__(NT) void k_histograms(const typename UInt<KB>::T* __restrict__ keys,
+                                                   uint64_t n, uint32_t bits, uint32_t nt,
+                                                   uint32_t copies, uint32_t* __restrict__ hist)
 {
     using K = typename UInt<KB>::T;
+    constexpr int U = 8;  // loads in flight per thread
     extern __shared__ uint32_t h[];
     const uint32_t sigma = 1u << bits, mask = sigma - 1, words = nt * sigma;
-    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < copies * words; i += NT) h[i] = 0;
     __syncthreads();
-    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        K x = keys[i];
-        for (uint32_t t = 0; t < nt; t++) {
-            uint32_t d = (uint32_t)(x >> (bits * (nt - 1 - t))) & mask;
-            atomicAdd(&h[t * sigma + d], 1u);
+    uint32_t* mine = h + ((threadIdx.x >> 6) % copies) * words;
+    const uint64_t step = (uint64_t)gridDim.x * NT * U;
+    for (uint64_t c = (uint64_t)blockIdx.x * NT * U; c < n; c += step) {
+        K x[U];
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            const uint64_t i = c + (uint64_t)j * NT + threadIdx.x;
+            x[j] = i < n ? keys[i] : (K)0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; j++) {
+            if (c + (uint64_t)j * NT + threadIdx.x < n) {
+                for (uint32_t t = 0; t < nt; t++) {
+                    const uint32_t d = (uint32_t)(x[j] >> (bits * (nt - 1 - t))) & mask;
+                    atomicAdd(&mine[t * sigma + d], 1u);
+                }
+            }
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
+    for (uint32_t i = threadIdx.x; i < words; i += NT) {
+        uint32_t v = 0;
+        for (uint32_t k = 0; k < copies; k++) v += h[k * words + i];
+        if (v) atomicAdd(&hist[i], v);
+    }
 }
 
 // Everything the rounds need that follows from the histograms alone, by the

@@ -281,10 +281,12 @@ template <int KB> int launch_histograms(const void* keys, const Geo& g, uint32_t
 {
     launch_fill(hist, (uint64_t)g.nt * g.sigma, 0, s);
     if (g.n == 0) return RADSORT_OK;
-    const uint32_t lds = 4 * g.nt * g.sigma;
-    uint32_t grid = (uint32_t)std::min<uint64_t>((g.n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_histograms<KB>, dim3(grid), dim3(256), lds, s,
-                       (const typename UInt<KB>::T*)keys, g.n, g.bits, g.nt, hist);
+    // copies of the counts per workgroup: as many as fit in 32 KB, up to one per wave
+    const uint32_t words = g.nt * g.sigma;
+    const uint32_t copies = std::max<uint32_t>(1, std::min<uint32_t>(8, 8192 / words));
+    uint32_t grid = (uint32_t)std::min<uint64_t>((g.n + 4095) / 4096, 2048);
+    hipLaunchKernelGGL((k_histograms<KB, 512>), dim3(grid), dim3(512), 4 * copies * words, s,
+                       (const typename UInt<KB>::T*)keys, g.n, g.bits, g.nt, copies, hist);
     return RADSORT_OK;
 }
 
@@ -471,7 +473,10 @@ template <int KB, int VB> struct Ops {
         a.spare_pi = st->pi(st->cur ^ 1);
         a.spare_blen = st->u32(st->L.blen);
         g_timer.mark(kFinBegin, 0, s);
-        int rc = finalize_parallel<KB, VB>(a, s);
+        const void* compact = (const void*)&k_fin_compact<KB, VB, fin_chunk<KB, VB>(), kCompactThreads>;
+        const int cap = resident_capacity(compact, kCompactThreads);
+        if (cap <= 0) return RADSORT_E_DEVICE;
+        int rc = finalize_parallel<KB, VB>(a, (uint32_t)cap, s) ? RADSORT_E_DEVICE : RADSORT_OK;
         g_timer.mark(kFinEnd, 0, s);
         return rc;
     }
