@@ -226,3 +226,51 @@ def test_ring_wraps_within_a_round():
     ok, ov = oracle.radsort(keys, vals, 256, 4, 1024)
     assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
     assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov)
+
+
+# ---------------------------------------------------------------- full sizes
+
+@pytest.mark.parametrize("b", [2048, 1024])
+def test_large_uniform_u32_matches_oracle(b):
+    """n = 2^28 uint32 + index: the benchmark's input, compared element by element
+    with the oracle's result; the out-of-place baseline on the same input too."""
+    n = 1 << 28
+    say(f"2^28 uint32 b={b}")
+    keys = workloads.uniform(workloads.SEED_LARGE, n, 4)
+    vals = np.arange(n, dtype=np.uint32)
+    ok, ov = oracle.radsort(keys, vals, 256, 4, b)
+    dk, dv = to_dev(keys), to_dev(vals)
+    radsort.sort_(dk, dv, block_elems=b, check=True)
+    assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
+    assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov)
+    if b == 2048:
+        dk, dv = to_dev(keys), to_dev(vals)
+        radsort.oop_sort_(dk, dv, block_elems=b, check=True)
+        assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
+        assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov)
+
+
+@pytest.mark.parametrize("dist", ["zipf", "equal", "sorted", "low20"])
+def test_structured_u64_2e30(dist):
+    """n = 2^30 uint64 keys + uint32 index, 8-bit digits (8 rounds), b = 1024.  The
+    oracle does not run at this size; the output is checked by the properties
+    that fix a stable sort's result: keys ascending (unsigned), indices
+    ascending within equal keys, the indices a permutation, and every key equal
+    to the input key at its index."""
+    n = 1 << 30
+    say(f"2^30 uint64 {dist}")
+    keys = workloads.make_t(dist, workloads.SEED_SKEWED, n, 8, DEV)
+    orig = keys.clone()
+    vals = torch.arange(n, dtype=torch.int32, device=DEV)
+    radsort.sort_(keys, vals, block_elems=1024, check=True)
+    flip = keys ^ (-(1 << 63))  # unsigned order as signed order
+    assert bool((flip[1:] >= flip[:-1]).all())
+    del flip
+    eq = keys[1:] == keys[:-1]
+    assert bool((vals[1:][eq] > vals[:-1][eq]).all())
+    del eq
+    seen = torch.zeros(n, dtype=torch.bool, device=DEV)
+    seen[vals.long()] = True
+    assert bool(seen.all())
+    del seen
+    assert bool((orig[vals.long()] == keys).all())

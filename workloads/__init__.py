@@ -126,3 +126,91 @@ DISTRIBUTIONS = {
 
 def make(dist: str, seed: int, n: int, key_bytes: int = 4) -> np.ndarray:
     return DISTRIBUTIONS[dist](seed, n, key_bytes)
+
+
+# ---- the same streams drawn with torch on a device ----------------------------------
+# For inputs too large to draw on the host in test time (n = 2^30).  Each function
+# returns the bytes of its host counterpart above, as a torch tensor (int32 /
+# int64 views of the unsigned keys); a CPU test checks the equality on small n.
+
+def _signed(u: int) -> int:
+    return u - (1 << 64) if u >= 1 << 63 else u
+
+
+def _shr(z, k: int):
+    """Logical right shift of int64 words that hold unsigned values."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _mix64_t(z):
+    z = z ^ _shr(z, 30)
+    z = z * _signed(int(_M1))
+    z = z ^ _shr(z, 27)
+    z = z * _signed(int(_M2))
+    return z ^ _shr(z, 31)
+
+
+def words_t(seed: int, n: int, device, start: int = 0, chunk: int = 1 << 26):
+    """``words(seed, n, start)`` as an int64 tensor on ``device``."""
+    import torch
+    out = torch.empty(n, dtype=torch.int64, device=device)
+    s = _signed(seed & 0xFFFFFFFFFFFFFFFF)
+    g = _signed(int(GAMMA))
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        idx = torch.arange(start + lo + 1, start + hi + 1, dtype=torch.int64, device=device)
+        out[lo:hi] = _mix64_t(idx * g + s)
+    return out
+
+
+def _high32_t(w):
+    import torch
+    h = _shr(w, 32)
+    return torch.where(h >= 1 << 31, h - (1 << 32), h).to(torch.int32)
+
+
+def uniform_t(seed: int, n: int, key_bytes: int, device):
+    w = words_t(seed, n, device)
+    return _high32_t(w) if key_bytes == 4 else w
+
+
+def zipf_t(seed: int, n: int, device, s: float = 1.1, distinct: int = 1 << 16,
+           key_bytes: int = 8):
+    import torch
+    ks = torch.arange(distinct, dtype=torch.int64, device=device)
+    values = _mix64_t(ks ^ _signed(seed))
+    if key_bytes == 4:
+        values = _high32_t(values)
+    w = torch.arange(1, distinct + 1, dtype=torch.float64, device=device) ** (-s)
+    cdf = torch.cumsum(w, 0)
+    cdf /= cdf[-1].clone()
+    out = torch.empty(n, dtype=values.dtype, device=device)
+    chunk = 1 << 24
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        u = _shr(words_t(seed ^ 0xA5A5A5A5, hi - lo, device, start=lo), 11).to(
+            torch.float64) * (1.0 / (1 << 53))
+        pick = torch.clamp(torch.searchsorted(cdf, u, right=True), max=distinct - 1)
+        out[lo:hi] = values[pick]
+    return out
+
+
+def make_t(dist: str, seed: int, n: int, key_bytes: int, device):
+    """``make(dist, seed, n, key_bytes)`` on ``device`` for the distributions of
+    the large structured inputs."""
+    import torch
+    if dist == "uniform":
+        return uniform_t(seed, n, key_bytes, device)
+    if dist == "zipf":
+        return zipf_t(seed, n, device, key_bytes=key_bytes)
+    if dist == "equal":
+        v = uniform_t(seed, 1, key_bytes, device)
+        return v.expand(n).contiguous()
+    if dist == "low20":
+        k = uniform_t(seed, n, key_bytes, device)
+        return k & ((1 << 20) - 1)
+    if dist == "sorted":
+        k = uniform_t(seed, n, key_bytes, device)
+        top = -(1 << 63) if key_bytes == 8 else -(1 << 31)
+        return torch.sort(k ^ top).values ^ top  # unsigned order via the flipped sign bit
+    raise ValueError(dist)
