@@ -58,6 +58,17 @@ typedef struct radsort_opts {
 
 #define RADSORT_MAX_ROUNDS 64
 
+/* Block size and digit width per size class for radsort_sort_segments: an array
+ * of n elements takes the first class c with ceil(log2 n) <= max_log2n[c].
+ * digit_bits must be 4, 8 or 11 and block_elems a power of two in [64, 65536]. */
+#define RADSORT_SEG_CLASSES 32
+typedef struct radsort_seg_tuning {
+    uint32_t classes;
+    uint32_t max_log2n[RADSORT_SEG_CLASSES];
+    uint32_t block_elems[RADSORT_SEG_CLASSES];
+    uint32_t digit_bits[RADSORT_SEG_CLASSES];
+} radsort_seg_tuning;
+
 typedef struct radsort_stats {
     uint64_t workspace_bytes;   /* extra device bytes of the last sort (peak extra memory) */
     uint64_t input_bytes;       /* n * (key_bytes + payload_bytes) of the last sort */
@@ -115,6 +126,36 @@ int radsort_oop_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
                            void* stream);
 uint64_t radsort_oop_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes,
                                      int digit_bits, const radsort_opts* opts);
+
+/*
+ * radsort_sort_segments -- sort nseg independent arrays in place, each stable and
+ * ascending by unsigned key with its payload, in one call on one stream.  Array i
+ * is elements [offsets[i], offsets[i+1]) of the key plane (and of the payload
+ * plane).  Arrays of at most 8192 elements (4096 for records of 12 or more bytes)
+ * are each sorted whole in LDS by one workgroup, with 8-bit digits and no
+ * workspace.  Larger arrays each run Radsort (Alg. 2: setup, n_t x sortPhase +
+ * fixupPhase, finalize), with the block size and digit width of their size class
+ * in `tuning` (NULL: b = 2^ceil(log2 sqrt n) in [64, 2048] and 8-bit digits, after
+ * the b in Theta(sqrt n) of Sec. 3), in launch forms that need no co-residency,
+ * spread over four streams forked from `stream` and joined back to it.
+ *   offsets      host array of nseg + 1 non-decreasing element offsets
+ *   offsets_dev  the same array in device memory (read by the small-array kernel)
+ *   opts         block_elems is ignored; workspace / workspace_bytes as for
+ *                radsort_sort_pairs (radsort_segments_workspace_bytes gives the
+ *                size; with a caller workspace nothing is allocated, so the call can
+ *                be captured into a HIP graph); flags: RADSORT_F_CHECK waits and
+ *                reports device errors
+ * Returns RADSORT_E_INVALID for a null or decreasing offsets array or bad widths,
+ * and the errors of radsort_sort_pairs otherwise.
+ */
+int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
+                          const uint64_t* offsets_dev, uint32_t nseg, int key_bytes,
+                          int payload_bytes, const radsort_seg_tuning* tuning,
+                          const radsort_opts* opts, void* stream);
+/* Workspace of radsort_sort_segments for these arrays, or 0 on a bad argument. */
+uint64_t radsort_segments_workspace_bytes(const uint64_t* offsets, uint32_t nseg, int key_bytes,
+                                          int payload_bytes, const radsort_seg_tuning* tuning,
+                                          const radsort_opts* opts);
 
 /*
  * radsort_histograms -- the up-front digit histograms alone: counts[t * sigma + c]

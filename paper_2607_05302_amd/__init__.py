@@ -31,7 +31,9 @@ ABI = [
     "radsort_strerror", "radsort_state_create", "radsort_state_setup", "radsort_state_round",
     "radsort_state_finalize", "radsort_state_finalize_sequential", "radsort_state_read",
     "radsort_state_logical", "radsort_state_dims", "radsort_state_destroy",
+    "radsort_sort_segments", "radsort_segments_workspace_bytes",
 ]
+SEG_CLASSES = 32
 
 
 class RadsortError(RuntimeError):
@@ -44,6 +46,12 @@ class Opts(ctypes.Structure):
     _fields_ = [("block_elems", ctypes.c_uint32), ("tile_elems", ctypes.c_uint32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("flags", ctypes.c_uint32)]
+
+
+class SegTuning(ctypes.Structure):
+    _fields_ = [("classes", ctypes.c_uint32), ("max_log2n", ctypes.c_uint32 * SEG_CLASSES),
+                ("block_elems", ctypes.c_uint32 * SEG_CLASSES),
+                ("digit_bits", ctypes.c_uint32 * SEG_CLASSES)]
 
 
 class Stats(ctypes.Structure):
@@ -87,6 +95,10 @@ def load(path: str | None = None):
         "radsort_state_logical": (i32, [vp, vp, vp, vp]),
         "radsort_state_dims": (i32, [vp, u32p, u32p, u32p]),
         "radsort_state_destroy": (i32, [vp]),
+        "radsort_sort_segments": (i32, [vp, vp, ctypes.POINTER(u64), vp, ctypes.c_uint32, i32, i32,
+                                        ctypes.POINTER(SegTuning), op, vp]),
+        "radsort_segments_workspace_bytes": (u64, [ctypes.POINTER(u64), ctypes.c_uint32, i32, i32,
+                                                   ctypes.POINTER(SegTuning), op]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -180,6 +192,68 @@ def oop_sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, w
             ctypes.c_void_p(keys.data_ptr()),
             ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
             keys.numel(), kb, vb, digit_bits, ctypes.byref(o), _stream(stream, keys.device))
+    _check(rc)
+    return keys, payload
+
+
+def seg_tuning(table):
+    """A SegTuning from [(max_log2n, block_elems, digit_bits), ...] in increasing
+    max_log2n, or None."""
+    if not table:
+        return None
+    t = SegTuning()
+    t.classes = len(table)
+    for c, (lg, b, bits) in enumerate(table):
+        t.max_log2n[c], t.block_elems[c], t.digit_bits[c] = lg, b, bits
+    return t
+
+
+def _offsets(offsets, device):
+    import numpy as np
+    import torch
+    host = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    dev = torch.from_numpy(host.view(np.int64)).to(device)
+    return host, dev
+
+
+def segments_workspace_bytes(offsets, key_bytes=4, payload_bytes=0, tuning="auto") -> int:
+    import numpy as np
+    if isinstance(tuning, str):
+        from .tune import load_table
+        tuning = load_table(key_bytes, payload_bytes)
+    host = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    t = seg_tuning(tuning)
+    return int(load().radsort_segments_workspace_bytes(
+        host.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(host) - 1, key_bytes,
+        payload_bytes, ctypes.byref(t) if t else None, None))
+
+
+def sort_segments_(keys, payload, offsets, tuning="auto", stream=None, workspace=None,
+                   check=False, offsets_dev=None):
+    """Sorts keys[offsets[i]:offsets[i+1]] (with the payload) in place for every i
+    (radsort_sort_segments).  tuning: [(max_log2n, block_elems, digit_bits), ...],
+    "auto" for the table the autotuner wrote for this record size (if any), or
+    None for the library's default.  With a caller workspace and offsets_dev
+    given, the call allocates nothing and can be captured into a graph."""
+    import numpy as np
+    kb, vb = _validate(keys, payload)
+    if isinstance(tuning, str):
+        from .tune import load_table
+        tuning = load_table(kb, vb)
+    host = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+    if offsets_dev is None:
+        host, offsets_dev = _offsets(host, keys.device)
+    if int(host[-1]) > keys.numel():
+        raise ValueError("offsets run past the arrays")
+    t = seg_tuning(tuning)
+    o = _opts(0, workspace, F_CHECK if check else 0)
+    with _device(keys):
+        rc = load().radsort_sort_segments(
+            ctypes.c_void_p(keys.data_ptr()),
+            ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
+            host.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+            ctypes.c_void_p(offsets_dev.data_ptr()), len(host) - 1, kb, vb,
+            ctypes.byref(t) if t else None, ctypes.byref(o), _stream(stream, keys.device))
     _check(rc)
     return keys, payload
 

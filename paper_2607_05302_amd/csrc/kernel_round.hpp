@@ -60,7 +60,8 @@ constexpr int kLookbackWin = 16;  // predecessors read per look-back step
 
 // Look-back words.  cnt[slot][d] holds a tile's count of digit d in bits 0-30
 // and, in bit 31, the parity of the tile's ring epoch (floor(tile / W)) inverted,
-// so that the zero-filled array reads as "not yet" for epoch 0.  done[slot] holds
+// so that the zero-filled array reads as "not yet" for epoch 0.  (16-bit words
+// would halve the look-back's reads, but measured slower on MI355X.)  done[slot] holds
 // tile + 1 once the tile has finished its look-back.  Slot = tile mod W.
 //
 // A slot is reused by tile T only after every tile of the super-tile of T - W,
@@ -95,12 +96,19 @@ struct TileArgs {
     uint32_t* done;          // [2^ring_log2]: tile + 1 once done, zeroed per round
     const uint32_t* stbase;  // [super-tile][sigma]: digit counts before each super-tile
     uint32_t* err;
+    uint32_t* tile_ctr;      // dynamic launches: next tile to claim, zero on entry
     uint32_t shift, bits, log2b, npi, ring_log2;
     uint32_t st_log2;        // tiles per super-tile: 2^st_log2
 };
 
 
-template <int KB, int VB, bool OOP, int FB, int SMAX, int WAVES, int ITEMS>
+// Two launch forms.  Persistent (DYN = false): a cooperative launch of as many
+// workgroups as are resident, each taking tiles in grid-stride order.  Dynamic
+// (DYN = true): one workgroup per tile, launched normally, each claiming the next
+// tile from a counter; a tile is claimed only by a running workgroup, so every
+// lower tile is already claimed by one and the waits still end.  The dynamic form
+// needs no co-residency, so several sorts can share the GPU.
+template <int KB, int VB, bool OOP, int FB, int SMAX, int WAVES, int ITEMS, bool DYN = false>
 __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
 {
     using K = typename UInt<KB>::T;
@@ -199,11 +207,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             if constexpr (VB != 0) vn[j] = valid ? *vp : (V)0;
         }
     };
-    block_info(blockIdx.x);
+    uint32_t first_tile = blockIdx.x, step = gridDim.x;
+    if constexpr (DYN) {
+        __shared__ uint32_t claimed;
+        if (tid == 0) claimed = add_agent(a.tile_ctr, 1u);
+        __syncthreads();
+        first_tile = claimed;
+        step = ntiles;  // one tile per workgroup
+    }
+    block_info(first_tile);
     __syncthreads();
-    load_tile(blockIdx.x);
+    load_tile(first_tile);
 
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (uint32_t tile = first_tile; tile < ntiles; tile += step) {
     K key[ITEMS];
     V val[ITEMS];
     uint32_t rk[ITEMS];  // wave-local rank << 12 | digit, or ~0 for an empty slot
@@ -220,7 +236,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
         for (uint32_t i = lane; i < SMAX; i += 64) myor[i] = 0;
     }
     // the next tile's block info: its loads are issued once this tile is staged
-    block_info(tile + gridDim.x);
+    block_info(tile + step);
 
     // Reuse of this tile's ring slot (see the look-back words above); the tiles
     // waited for started W tiles earlier, so the wait almost never polls twice.
@@ -317,7 +333,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     }
     __syncthreads();
     // registers are free again: issue the next tile's loads
-    load_tile(tile + gridDim.x);
+    load_tile(tile + step);
 
     uint32_t* base = wh;                  // per-digit data reusing the wave counts
     uint32_t* nfw = wh + SMAX;

@@ -410,10 +410,12 @@ __device__ __forceinline__ void gap_before(const uint32_t* Pidx, const uint32_t*
 }
 
 // One chunk = CHUNK consecutive element positions of the A blocks (whole blocks,
-// or a part of one block when b > CHUNK), held in registers.  The kernel is
-// persistent and launched cooperatively: workgroup w takes chunks w, w + G, ...,
-// and a chunk waits only for lower chunks to have loaded, so the waits end.
-template <int KB, int VB, int CHUNK, int NT>
+// or a part of one block when b > CHUNK), held in registers.  A chunk waits only
+// for lower chunks to have loaded.  Persistent form (DYN = false): launched
+// cooperatively, workgroup w takes chunks w, w + G, ...  Dynamic form: one
+// workgroup per chunk, each claiming the next chunk from a counter (flags[chunks],
+// zero on entry), so every lower chunk is held by a running workgroup.
+template <int KB, int VB, int CHUNK, int NT, bool DYN = false>
 __global__ __launch_bounds__(NT) void k_fin_compact(FinArgs<KB, VB> a, const uint32_t* gap,
                                                     uint32_t* flags, uint32_t chunks)
 {
@@ -424,7 +426,15 @@ __global__ __launch_bounds__(NT) void k_fin_compact(FinArgs<KB, VB> a, const uin
     __shared__ uint32_t bG[MAXB], bL[MAXB];
     const uint32_t tid = threadIdx.x, b = 1u << a.log2b, sigma = a.sigma, log2b = a.log2b;
     const uint64_t total = (a.n >> log2b) << log2b;  // positions of the full A blocks
-    for (uint32_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    uint32_t c0 = blockIdx.x, step = gridDim.x;
+    if constexpr (DYN) {
+        __shared__ uint32_t claimed;
+        if (tid == 0) claimed = add_agent(flags + chunks, 1u);
+        __syncthreads();
+        c0 = claimed;
+        step = chunks;
+    }
+    for (uint32_t c = c0; c < chunks; c += step) {
         __syncthreads();  // the previous chunk is done with bG / bL
         const uint64_t p0 = (uint64_t)c * CHUNK;
         const uint32_t cnt = (uint32_t)min<uint64_t>(CHUNK, total - p0);
@@ -519,6 +529,7 @@ inline void fin_scan(uint32_t* a, uint32_t count, uint32_t* sums, hipStream_t s)
 constexpr int kCompactThreads = 512;
 template <int KB, int VB> constexpr int fin_chunk() { return (KB + VB >= 12) ? 4096 : 8192; }
 
+// compact_grid = 0 selects the dynamic compaction (one workgroup per chunk)
 template <int KB, int VB>
 int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
 {
@@ -561,9 +572,11 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
     uint32_t chunks = (uint32_t)((positions + CHUNK - 1) / CHUNK);
     hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
                        dim3(256), 0, s, f.flags, f.nflags, 0u);
-    if (chunks) {
+    if (chunks && compact_grid == 0) {
+        hipLaunchKernelGGL((k_fin_compact<KB, VB, CHUNK, kCompactThreads, true>), dim3(chunks),
+                           dim3(kCompactThreads), 0, s, a, gap, f.flags, chunks);
+    } else if (chunks) {
         const uint32_t grid = std::min(chunks, compact_grid);
-        if (!grid) return -1;
         void* args[] = {(void*)&a, (void*)&gap, (void*)&f.flags, (void*)&chunks};
         if (hipLaunchCooperativeKernel((const void*)&k_fin_compact<KB, VB, CHUNK, kCompactThreads>,
                                        dim3(grid), dim3(kCompactThreads), args, 0, s) != hipSuccess)

@@ -10,12 +10,14 @@
 #include <mutex>
 #include <new>
 #include <utility>
+#include <vector>
 
 #include "../../include/radsort.h"
 #include "common.hpp"
 #include "kernels_state.hpp"
 #include "kernel_round.hpp"
 #include "kernels_prefix.hpp"
+#include "kernels_small.hpp"
 #include "kernels_finalize.hpp"
 #include "kernels_finalize_seq.hpp"
 
@@ -262,6 +264,7 @@ struct radsort_state {
     uint32_t rounds_done = 0;  // rounds since setup
     int cur = 0;               // which pi buffer holds pi
     bool is_setup = false;
+    bool dynamic = false;      // launch forms that need no co-residency (shared GPU)
 
     uint32_t* u32(uint64_t off) const { return (uint32_t*)(ws + off); }
     uint32_t* pi(int which) const { return u32(which ? L.pi1 : L.pi0); }
@@ -351,13 +354,36 @@ void launch_super_counts(const Geo& g, const typename UInt<KB>::T* Ak,
                        0, s, stcnt, csum, supers, g.sigma);
 }
 
+// One workgroup per tile, claimed from a counter (no co-residency needed).
+template <typename Args>
+int launch_dynamic(const void* kern, uint32_t tiles, uint32_t threads, Args& a, hipStream_t s)
+{
+    void* args[] = {(void*)&a};
+    RS_HIP(hipLaunchKernel(kern, dim3(tiles), dim3(threads), args, 0, s));
+    return RADSORT_OK;
+}
+
 template <int KB, int VB, bool OOP>
-int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s)
+int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = false)
 {
     using N = TileCfg<KB, VB, false>;
     using Wd = TileCfg<KB, VB, true>;
     const uint32_t tiles = OOP ? (uint32_t)((g.n + g.E - 1) / g.E) : g.tiles;
     if (tiles == 0) return RADSORT_OK;
+    if (dyn) {
+        launch_fill(a.tile_ctr, 1, 0, s);
+        if (g.bits == 8)
+            return launch_dynamic(
+                (const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS, true>, tiles,
+                64 * N::WAVES, a, s);
+        if (g.bits < 8)
+            return launch_dynamic(
+                (const void*)&k_round<KB, VB, OOP, 0, 256, N::WAVES, N::ITEMS, true>, tiles,
+                64 * N::WAVES, a, s);
+        return launch_dynamic(
+            (const void*)&k_round<KB, VB, OOP, 0, 2048, Wd::WAVES, Wd::ITEMS, true>, tiles,
+            64 * Wd::WAVES, a, s);
+    }
     if (g.bits == 8)
         return launch_persistent((const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS>,
                                  tiles, 64 * N::WAVES, a, s);
@@ -411,6 +437,7 @@ template <int KB, int VB> struct Ops {
         a.agg = (uint32_t*)(st->ws + st->L.agg);
         a.done = (uint32_t*)(st->ws + st->L.done);
         a.err = st->err();
+        a.tile_ctr = st->err() + 1;
         a.shift = g.bits * (g.nt - 1 - t);
         a.bits = g.bits;
         a.log2b = g.log2b;
@@ -419,12 +446,12 @@ template <int KB, int VB> struct Ops {
         a.st_log2 = g.st_log2;
         uint32_t* stcnt = (uint32_t*)(st->ws + st->L.stcnt);
         a.stbase = stcnt;
-        launch_fill(a.agg, st->L.ring_bytes / 4, 0, s);
+        launch_fill((uint32_t*)a.agg, st->L.ring_bytes / 4, 0, s);
         g_timer.mark(kCountBegin, r, s);
         launch_super_counts<KB, false>(g, a.Ak, a.Tk, a.pi_old, a.blen, a.f_in, a.shift, stcnt,
                                        st->u32(st->L.csum), a.err, s);
         g_timer.mark(kRoundBegin, r, s);
-        int rc = launch_round_t<KB, VB, false>(g, a, s);
+        int rc = launch_round_t<KB, VB, false>(g, a, s, st->dynamic);
         if (rc) return rc;
         g_timer.mark(kRoundEnd, r, s);
         uint32_t grid = (uint32_t)std::min<uint64_t>((g.npi + 255) / 256, 4096);
@@ -473,9 +500,13 @@ template <int KB, int VB> struct Ops {
         a.spare_pi = st->pi(st->cur ^ 1);
         a.spare_blen = st->u32(st->L.blen);
         g_timer.mark(kFinBegin, 0, s);
-        const void* compact = (const void*)&k_fin_compact<KB, VB, fin_chunk<KB, VB>(), kCompactThreads>;
-        const int cap = resident_capacity(compact, kCompactThreads);
-        if (cap <= 0) return RADSORT_E_DEVICE;
+        int cap = 0;  // 0: the dynamic compaction
+        if (!st->dynamic) {
+            const void* compact =
+                (const void*)&k_fin_compact<KB, VB, fin_chunk<KB, VB>(), kCompactThreads>;
+            cap = resident_capacity(compact, kCompactThreads);
+            if (cap <= 0) return RADSORT_E_DEVICE;
+        }
         int rc = finalize_parallel<KB, VB>(a, (uint32_t)cap, s) ? RADSORT_E_DEVICE : RADSORT_OK;
         g_timer.mark(kFinEnd, 0, s);
         return rc;
@@ -522,6 +553,7 @@ template <int KB, int VB> struct Ops {
             a.agg = (uint32_t*)(ws + L.agg);
             a.done = (uint32_t*)(ws + L.done);
             a.err = ctr + g.nt;
+            a.tile_ctr = ctr + g.nt + 1;
             a.shift = g.bits * (g.nt - 1 - t);
             a.bits = g.bits;
             a.log2b = g.log2b;
@@ -529,7 +561,7 @@ template <int KB, int VB> struct Ops {
             a.st_log2 = g.st_log2;
             uint32_t* stcnt = (uint32_t*)(ws + L.stcnt);
             a.stbase = stcnt;
-            launch_fill(a.agg, L.ring_bytes / 4, 0, s);
+            launch_fill((uint32_t*)a.agg, L.ring_bytes / 4, 0, s);
             g_timer.mark(kCountBegin, r, s);
             launch_super_counts<KB, true>(g, a.Ak, (const K*)nullptr, nullptr, nullptr, nullptr,
                                           a.shift, stcnt, (uint32_t*)(ws + L.csum), a.err, s);
@@ -606,6 +638,159 @@ int read_err(radsort_state* st, hipStream_t s, uint32_t* bits)
 }  // namespace
 
 // ---- C ABI ---------------------------------------------------------------------------
+
+
+// ---- many arrays at once ---------------------------------------------------------
+
+// Arrays of at most kSmallE<KB, VB> elements are sorted whole in LDS by
+// k_sort_small (one workgroup each, no workspace).  Larger ones run the Radsort
+// steps in the dynamic launch form, spread over kSegLanes streams forked from the
+// caller's stream, each lane with its own workspace.
+constexpr uint32_t kSegLanes = 4;
+template <int KB, int VB> struct SmallCfg {
+    static constexpr int WAVES = 8;
+    static constexpr int ITEMS = (KB + VB >= 12) ? 8 : 16;
+    static constexpr uint32_t E = 64 * WAVES * ITEMS;
+};
+uint32_t small_elems(uint32_t kb, uint32_t vb) { return (kb + vb >= 12) ? 4096u : 8192u; }
+
+struct SegChoice {
+    uint32_t b, bits;
+};
+
+// block size and digit width for an array of n elements: the first class of the
+// table whose max_log2n covers ceil(log2 n), else b = 2^ceil(log2 sqrt n) in
+// [64, 2048] and 8-bit digits (b in Theta(sqrt n), Sec. 3)
+SegChoice seg_choice(const radsort_seg_tuning* t, uint64_t n)
+{
+    const uint32_t lg = (uint32_t)ilog2(n);
+    if (t)
+        for (uint32_t c = 0; c < t->classes && c < RADSORT_SEG_CLASSES; c++)
+            if (lg <= t->max_log2n[c]) return {t->block_elems[c], t->digit_bits[c]};
+    const uint32_t b = std::min<uint32_t>(2048u, std::max<uint32_t>(64u, 1u << ((lg + 1) / 2)));
+    return {b, 8u};
+}
+
+struct SegPlan {
+    std::vector<uint32_t> large;  // indices of the arrays that run the Radsort steps
+    std::vector<uint32_t> lane;   // lane of each of them
+    std::vector<SegChoice> choice;
+    uint64_t lane_off[kSegLanes] = {}, lane_bytes[kSegLanes] = {};
+    uint64_t total = 0;
+    bool any_small = false;
+};
+
+int make_seg_plan(SegPlan& P, const uint64_t* off, uint32_t nseg, int kb, int vb,
+                  const radsort_seg_tuning* tuning, const radsort_opts* opts)
+{
+    const uint32_t se = small_elems(kb, vb);
+    std::vector<std::pair<uint64_t, uint32_t>> big;
+    for (uint32_t i = 0; i < nseg; i++) {
+        if (off[i + 1] < off[i]) return RADSORT_E_INVALID;
+        const uint64_t n = off[i + 1] - off[i];
+        if (n <= 1) continue;
+        if (n <= se) {
+            P.any_small = true;
+            continue;
+        }
+        big.push_back({n, i});
+    }
+    // largest first, each to the lane with the fewest elements so far
+    std::sort(big.begin(), big.end(), [](auto& x, auto& y) { return x.first > y.first; });
+    uint64_t load[kSegLanes] = {};
+    for (auto& [n, i] : big) {
+        uint32_t l = 0;
+        for (uint32_t k = 1; k < kSegLanes; k++)
+            if (load[k] < load[l]) l = k;
+        load[l] += n;
+        SegChoice c = seg_choice(tuning, n);
+        radsort_opts o = opts ? *opts : radsort_opts{};
+        o.block_elems = c.b;
+        Geo g;
+        int rc = make_geo(g, n, kb, vb, (int)c.bits, &o);
+        if (rc) return rc;
+        P.lane_bytes[l] = std::max(P.lane_bytes[l], make_layout(g, false).total);
+        P.large.push_back(i);
+        P.lane.push_back(l);
+        P.choice.push_back(c);
+    }
+    uint64_t o = 256;  // the small kernel's error word
+    for (uint32_t l = 0; l < kSegLanes; l++) {
+        P.lane_off[l] = o;
+        o = align_up(o + P.lane_bytes[l], 256);
+    }
+    P.total = o;
+    return RADSORT_OK;
+}
+
+struct LaneStreams {
+    hipStream_t s[kSegLanes];
+    hipEvent_t fork, join[kSegLanes];
+};
+
+// streams and events of the lanes, one set per device, kept until the process ends
+int lane_streams(LaneStreams** out)
+{
+    static std::mutex mu;
+    static std::map<int, LaneStreams*> sets;
+    int dev = 0;
+    RS_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = sets.find(dev);
+    if (it != sets.end()) {
+        *out = it->second;
+        return RADSORT_OK;
+    }
+    LaneStreams* L = new (std::nothrow) LaneStreams();
+    if (!L) return RADSORT_E_NOMEM;
+    for (uint32_t l = 0; l < kSegLanes; l++) {
+        RS_HIP(hipStreamCreateWithFlags(&L->s[l], hipStreamNonBlocking));
+        RS_HIP(hipEventCreateWithFlags(&L->join[l], hipEventDisableTiming));
+    }
+    RS_HIP(hipEventCreateWithFlags(&L->fork, hipEventDisableTiming));
+    sets[dev] = L;
+    *out = L;
+    return RADSORT_OK;
+}
+
+template <int KB, int VB> struct DoSmall {
+    static int run(void* keys, void* vals, const uint64_t* offsets_dev, uint32_t nseg,
+                   uint32_t* err, hipStream_t s)
+    {
+        using C = SmallCfg<KB, VB>;
+        const uint32_t nt = (8 * KB + 7) / 8;
+        hipLaunchKernelGGL((k_sort_small<KB, VB, C::WAVES, C::ITEMS>), dim3(nseg),
+                           dim3(64 * C::WAVES), 0, s, (typename UInt<KB>::T*)keys,
+                           (typename Payload<VB>::T*)vals, offsets_dev, nseg, 8u, nt, err);
+        return RADSORT_OK;
+    }
+};
+
+__global__ void k_or_error(const uint32_t* src, uint32_t* dst)
+{
+    if (threadIdx.x == 0 && *src) atomicOr(dst, *src);
+}
+
+// the Radsort steps of one array on stream s, in the dynamic launch form; its
+// device error bits are ORed into *errs
+int run_one(void* keys, void* vals, uint64_t n, int kb, int vb, SegChoice c, uint8_t* ws,
+            uint64_t ws_bytes, uint32_t* errs, hipStream_t s)
+{
+    radsort_opts o{};
+    o.block_elems = c.b;
+    o.workspace = ws;
+    o.workspace_bytes = ws_bytes;
+    radsort_state* st = nullptr;
+    int rc = radsort_state_create(&st, keys, vals, n, kb, vb, (int)c.bits, &o);
+    if (rc) return rc;
+    st->dynamic = true;
+    rc = radsort_state_setup(st, s);
+    for (uint32_t r = 0; !rc && r < st->g.nt; r++) rc = radsort_state_round(st, s);
+    if (!rc) rc = radsort_state_finalize(st, s);
+    if (!rc) hipLaunchKernelGGL(k_or_error, dim3(1), dim3(64), 0, s, st->err(), errs);
+    radsort_state_destroy(st);
+    return rc;
+}
 
 extern "C" {
 
@@ -873,6 +1058,93 @@ const char* radsort_strerror(int code)
     case RADSORT_E_TIMEOUT: return "a device-side wait gave up (protocol error)";
     default: return "unknown error";
     }
+}
+
+uint64_t radsort_segments_workspace_bytes(const uint64_t* offsets, uint32_t nseg, int key_bytes,
+                                          int payload_bytes, const radsort_seg_tuning* tuning,
+                                          const radsort_opts* opts)
+{
+    if (!offsets || (key_bytes != 4 && key_bytes != 8)) return 0;
+    SegPlan P;
+    if (make_seg_plan(P, offsets, nseg, key_bytes, payload_bytes, tuning, opts)) return 0;
+    return P.total;
+}
+
+int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
+                          const uint64_t* offsets_dev, uint32_t nseg, int key_bytes,
+                          int payload_bytes, const radsort_seg_tuning* tuning,
+                          const radsort_opts* opts, void* stream)
+{
+    if (!offsets || (nseg && !offsets_dev)) return RADSORT_E_INVALID;
+    if (key_bytes != 4 && key_bytes != 8) return RADSORT_E_INVALID;
+    if (payload_bytes != 0 && payload_bytes != 4 && payload_bytes != 8) return RADSORT_E_INVALID;
+    if (nseg == 0 || offsets[nseg] == offsets[0]) return RADSORT_OK;
+    int rc = check_args(keys, payload, offsets[nseg], payload_bytes);
+    if (rc) return rc;
+    SegPlan P;
+    rc = make_seg_plan(P, offsets, nseg, key_bytes, payload_bytes, tuning, opts);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* ws = opts ? (uint8_t*)opts->workspace : nullptr;
+    bool own = false;
+    if (ws) {
+        if (opts->workspace_bytes < P.total) return RADSORT_E_NOMEM;
+    } else {
+        hipError_t e = hipMalloc((void**)&ws, P.total);
+        if (e != hipSuccess) {
+            g_last_hip = e;
+            return RADSORT_E_NOMEM;
+        }
+        own = true;
+    }
+    uint32_t* err_small = (uint32_t*)ws;  // [0]: small arrays, [1 + l]: lane l
+    launch_fill(err_small, 1 + kSegLanes, 0, s);
+    if (P.any_small) {
+        rc = dispatch<DoSmall>(key_bytes, payload_bytes, keys, payload, offsets_dev, nseg,
+                               err_small, s);
+    }
+    if (!rc && !P.large.empty()) {
+        LaneStreams* L = nullptr;
+        rc = lane_streams(&L);
+        if (!rc) {
+            // fork the lanes from the caller's stream, join them back at the end
+            if (hipEventRecord(L->fork, s) != hipSuccess) rc = RADSORT_E_DEVICE;
+            for (uint32_t l = 0; !rc && l < kSegLanes; l++)
+                if (hipStreamWaitEvent(L->s[l], L->fork, 0) != hipSuccess) rc = RADSORT_E_DEVICE;
+            const uint64_t kb = key_bytes, vb = payload_bytes;
+            for (size_t k = 0; !rc && k < P.large.size(); k++) {
+                const uint32_t i = P.large[k], l = P.lane[k];
+                void* kp = (uint8_t*)keys + offsets[i] * kb;
+                void* vp = payload ? (uint8_t*)payload + offsets[i] * vb : nullptr;
+                rc = run_one(kp, vp, offsets[i + 1] - offsets[i], key_bytes, payload_bytes,
+                             P.choice[k], ws + P.lane_off[l], P.lane_bytes[l], err_small + 1 + l,
+                             L->s[l]);
+            }
+            for (uint32_t l = 0; l < kSegLanes; l++) {
+                if (hipEventRecord(L->join[l], L->s[l]) != hipSuccess && !rc) rc = RADSORT_E_DEVICE;
+                if (hipStreamWaitEvent(s, L->join[l], 0) != hipSuccess && !rc) rc = RADSORT_E_DEVICE;
+            }
+        }
+    }
+    g_stats.timed = 0;
+    g_stats.workspace_bytes = P.total;
+    g_stats.input_bytes = (offsets[nseg] - offsets[0]) * (uint64_t)(key_bytes + payload_bytes);
+    const bool check = opts && (opts->flags & RADSORT_F_CHECK);
+    if (!rc && (check || own)) {
+        // every lane's error word and the small kernel's
+        uint32_t e = 0;
+        std::vector<uint32_t> words(1 + kSegLanes, 0);
+        RS_HIP(hipStreamSynchronize(s));
+        RS_HIP(hipMemcpy(words.data(), err_small, 4 * words.size(), hipMemcpyDeviceToHost));
+        for (uint32_t w : words) e |= w;
+        g_stats.error_bits = e;
+        if (e) rc = RADSORT_E_TIMEOUT;
+    }
+    if (own) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(ws);
+    }
+    return rc;
 }
 
 }  // extern "C"
