@@ -91,8 +91,12 @@ def main():
     ap.add_argument("--no-oop", action="store_true", help="skip the out-of-place baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["single", "segments"], default="single",
-                    help="segments: 4096 uint32 arrays of log-uniform sizes in one call")
+    ap.add_argument("--workload", choices=["single", "segments", "serving"], default="single",
+                    help="segments: 4096 uint32 arrays of log-uniform sizes in one call; "
+                         "serving: a stream of sort requests admitted by memory footprint")
+    ap.add_argument("--requests", type=int, default=400, help="serving: requests in the trace")
+    ap.add_argument("--rate", type=float, default=800.0, help="serving: offered requests/s")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device memory budget")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scales HBM counters)")
     args = ap.parse_args()
@@ -111,6 +115,8 @@ def main():
 
     if args.workload == "segments":
         return bench_segments(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     n = 1 << args.log2n
     b, bits, kb, vb = args.block, 8, 4, 4
     dev = torch.device("cuda:0")
@@ -352,6 +358,46 @@ def bench_segments(args):
         "peak_extra_bytes": ws_bytes,
         "peak_extra_frac_of_input": ws_bytes / (total * 8),
         "verified": ok,
+    }
+    print(json.dumps(out), flush=True)
+
+
+SERVE_SEED = 0x5EED0005
+
+
+def bench_serving(args):
+    """Poisson arrivals of sort requests (sizes log-uniform in [2^12, 2^28], uint32 or
+    uint64 keys with a uint32 index payload), served under a device memory budget
+    by Radsort and, on the same trace, by the out-of-place baseline."""
+    import torch
+
+    from paper_2607_05302_amd import serve
+
+    torch.cuda.set_device(0)
+    trace = serve.make_trace(SERVE_SEED, args.requests, args.rate)
+    res = {}
+    for method in ("radsort", "oop"):
+        srv = serve.Server(method, budget=args.budget_gb * 1e9, slots=16)
+        srv.run(trace[: min(8, len(trace))])  # warm-up: kernels loaded, streams made
+        torch.cuda.empty_cache()
+        log(f"bench: serving {len(trace)} requests with {method}")
+        out = srv.run(trace)
+        res[method] = serve.summarize(trace, out)
+        log(f"bench: {method}: {res[method]}")
+        del srv
+        torch.cuda.empty_cache()
+    r = res["radsort"]
+    out = {
+        "metric": "sort serving: keys/s and p50/p99 latency, Poisson arrivals, sizes log-uniform "
+                  "in [2^12, 2^28], 50/50 uint32/uint64 keys, 64 GB budget, Radsort vs out-of-place",
+        "value": r["keys_per_s"], "unit": "keys/s", "n_gpus": 1, "steps": args.requests,
+        "warmup": 8, "ms_per_step": r["span_ms"] / args.requests, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
+        "config": {"workload": f"{args.requests} requests at {args.rate:g}/s offered "
+                               f"(splitmix64 seed {SERVE_SEED:#x}), budget {args.budget_gb:g} GB, "
+                               f"16 slots", "offered_rps": serve.offered_load(trace)},
+        "radsort": r, "oop": res["oop"],
+        "p99_ratio_oop_over_radsort": res["oop"]["p99_ms"] / r["p99_ms"],
     }
     print(json.dumps(out), flush=True)
 

@@ -46,6 +46,9 @@ extern "C" {
 #define RADSORT_F_CHECK 1u          /* wait for the stream and report device-side errors */
 #define RADSORT_F_TIMING 2u         /* record HIP events around each phase on the stream;
                                        radsort_last_stats() waits for them and reports */
+#define RADSORT_F_SHARED 4u         /* the GPU runs other work at the same time: use launch
+                                       forms that need no co-resident grid (one workgroup
+                                       per tile, tiles claimed in order) */
 
 typedef struct radsort_opts {
     uint32_t block_elems;     /* b: block size in elements, a power of two in [64, 65536];

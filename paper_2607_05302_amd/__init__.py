@@ -21,7 +21,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libradsort.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_TIMEOUT = 0, -1, -2, -3, -4, -5
-F_CHECK, F_TIMING = 1, 2
+F_CHECK, F_TIMING, F_SHARED = 1, 2, 4
 MAX_ROUNDS = 64
 
 # every function declared in include/radsort.h
@@ -169,10 +169,12 @@ def oop_workspace_bytes(n, key_bytes=4, payload_bytes=0, digit_bits=8, block_ele
 
 
 def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, workspace=None,
-          check=False, timing=False):
-    """Radsort in place on the current stream (radsort_sort_pairs)."""
+          check=False, timing=False, shared=False):
+    """Radsort in place on the current stream (radsort_sort_pairs).  shared: other
+    work runs on the GPU at the same time (RADSORT_F_SHARED)."""
     kb, vb = _validate(keys, payload)
-    o = _opts(block_elems, workspace, (F_CHECK if check else 0) | (F_TIMING if timing else 0))
+    o = _opts(block_elems, workspace, (F_CHECK if check else 0) | (F_TIMING if timing else 0)
+              | (F_SHARED if shared else 0))
     with _device(keys):
         rc = load().radsort_sort_pairs(
             ctypes.c_void_p(keys.data_ptr()),
@@ -183,10 +185,11 @@ def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, works
 
 
 def oop_sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, workspace=None,
-              check=False, timing=False):
+              check=False, timing=False, shared=False):
     """The out-of-place LSD baseline of Alg. 1, in place from the caller's view."""
     kb, vb = _validate(keys, payload)
-    o = _opts(block_elems, workspace, (F_CHECK if check else 0) | (F_TIMING if timing else 0))
+    o = _opts(block_elems, workspace, (F_CHECK if check else 0) | (F_TIMING if timing else 0)
+              | (F_SHARED if shared else 0))
     with _device(keys):
         rc = load().radsort_oop_sort_pairs(
             ctypes.c_void_p(keys.data_ptr()),

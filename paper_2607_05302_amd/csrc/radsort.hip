@@ -528,7 +528,7 @@ template <int KB, int VB> struct Ops {
 
     // Alg. 1 rounds, ping-ponging between the caller's arrays and the workspace
     static int oop_sort(void* keys, void* vals, const Geo& g, const Layout& L, uint8_t* ws,
-                        hipStream_t s)
+                        bool dyn, hipStream_t s)
     {
         uint32_t* hist = (uint32_t*)(ws + L.hist);
         PlanPtrs p{(uint32_t*)(ws + L.S), (uint32_t*)(ws + L.Pidx), (uint32_t*)(ws + L.Plen),
@@ -566,7 +566,7 @@ template <int KB, int VB> struct Ops {
             launch_super_counts<KB, true>(g, a.Ak, (const K*)nullptr, nullptr, nullptr, nullptr,
                                           a.shift, stcnt, (uint32_t*)(ws + L.csum), a.err, s);
             g_timer.mark(kRoundBegin, r, s);
-            int rc = launch_round_t<KB, VB, true>(g, a, s);
+            int rc = launch_round_t<KB, VB, true>(g, a, s, dyn);
             if (rc) return rc;
             g_timer.mark(kRoundEnd, r, s);
         }
@@ -611,9 +611,10 @@ template <int KB, int VB> struct DoLogical {
     }
 };
 template <int KB, int VB> struct DoOop {
-    static int run(void* k, void* v, const Geo& g, const Layout& L, uint8_t* ws, hipStream_t s)
+    static int run(void* k, void* v, const Geo& g, const Layout& L, uint8_t* ws, bool dyn,
+                   hipStream_t s)
     {
-        return Ops<KB, VB>::oop_sort(k, v, g, L, ws, s);
+        return Ops<KB, VB>::oop_sort(k, v, g, L, ws, dyn, s);
     }
 };
 
@@ -942,6 +943,7 @@ int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes, int
     radsort_state* st = nullptr;
     rc = radsort_state_create(&st, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts);
     if (rc) return rc;
+    st->dynamic = opts && (opts->flags & RADSORT_F_SHARED);
     hipStream_t s = (hipStream_t)stream;
     const bool timing = opts && (opts->flags & RADSORT_F_TIMING);
     if (timing) g_timer.begin();
@@ -991,7 +993,8 @@ int radsort_oop_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
     }
     const bool timing = opts && (opts->flags & RADSORT_F_TIMING);
     if (timing) g_timer.begin();
-    rc = dispatch<DoOop>(g.kb, g.vb, keys, payload, g, L, ws, s);
+    const bool dyn = opts && (opts->flags & RADSORT_F_SHARED);
+    rc = dispatch<DoOop>(g.kb, g.vb, keys, payload, g, L, ws, dyn, s);
     g_timer.end();
     g_stats.timed = 0;
     if (!rc) {
