@@ -165,7 +165,7 @@ Layout make_layout(const Geo& g, bool oop)
     // Finalize reuses all of it.
     const uint64_t supers = oop ? g.oop_supers : g.supers;
     const uint64_t agg_bytes = 4ull * g.ring_w * sig;
-    const uint64_t done_bytes = align_up(4ull * g.ring_w, 256);
+    const uint64_t done_bytes = align_up(4ull * g.ring_w + 4, 256);  // + the tile counter
     const uint64_t csum_bytes = align_up(4ull * ((supers + kScanRows - 1) / kScanRows) * sig, 256);
     L.ring_bytes = agg_bytes + done_bytes + csum_bytes;
     const uint64_t st_bytes = align_up(4ull * supers * sig, 256);
@@ -371,7 +371,6 @@ int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = 
     const uint32_t tiles = OOP ? (uint32_t)((g.n + g.E - 1) / g.E) : g.tiles;
     if (tiles == 0) return RADSORT_OK;
     if (dyn) {
-        launch_fill(a.tile_ctr, 1, 0, s);
         if (g.bits == 8)
             return launch_dynamic(
                 (const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS, true>, tiles,
@@ -437,7 +436,7 @@ template <int KB, int VB> struct Ops {
         a.agg = (uint32_t*)(st->ws + st->L.agg);
         a.done = (uint32_t*)(st->ws + st->L.done);
         a.err = st->err();
-        a.tile_ctr = st->err() + 1;
+        a.tile_ctr = a.done + g.ring_w;  // zeroed with the ring
         a.shift = g.bits * (g.nt - 1 - t);
         a.bits = g.bits;
         a.log2b = g.log2b;
@@ -553,7 +552,7 @@ template <int KB, int VB> struct Ops {
             a.agg = (uint32_t*)(ws + L.agg);
             a.done = (uint32_t*)(ws + L.done);
             a.err = ctr + g.nt;
-            a.tile_ctr = ctr + g.nt + 1;
+            a.tile_ctr = a.done + g.ring_w;  // zeroed with the ring
             a.shift = g.bits * (g.nt - 1 - t);
             a.bits = g.bits;
             a.log2b = g.log2b;
