@@ -122,6 +122,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     constexpr int PTAB = OR_RANK ? 4 * TBL : 0;  // words of the pointer table
     constexpr int UNI = (E / 2 + 2 * SMAX) > PTAB ? (E / 2 + 2 * SMAX) : PTAB;
     static_assert(E <= 65536, "slot indices are 16-bit");
+    static_assert((E & (E - 1)) == 0, "tiles and super-tiles are powers of two");
     static_assert(WAVES >= 4, "per-digit scratch reuses the per-wave counts");
     static_assert(!OR_RANK || E * KB >= WAVES * SMAX * 8, "OR tables live in the key stage");
 
