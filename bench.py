@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="serving: requests in the trace")
     ap.add_argument("--rate", type=float, default=800.0, help="serving: offered requests/s")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device memory budget")
+    ap.add_argument("--slots", type=int, default=8, help="serving: requests on the GPU at once")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scales HBM counters)")
     args = ap.parse_args()
@@ -377,7 +378,7 @@ def bench_serving(args):
     trace = serve.make_trace(SERVE_SEED, args.requests, args.rate)
     res = {}
     for method in ("radsort", "oop"):
-        srv = serve.Server(method, budget=args.budget_gb * 1e9, slots=16)
+        srv = serve.Server(method, budget=args.budget_gb * 1e9, slots=args.slots)
         srv.run(trace[: min(8, len(trace))])  # warm-up: kernels loaded, streams made
         torch.cuda.empty_cache()
         log(f"bench: serving {len(trace)} requests with {method}")
@@ -395,7 +396,7 @@ def bench_serving(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
         "config": {"workload": f"{args.requests} requests at {args.rate:g}/s offered "
                                f"(splitmix64 seed {SERVE_SEED:#x}), budget {args.budget_gb:g} GB, "
-                               f"16 slots", "offered_rps": serve.offered_load(trace)},
+                               f"{args.slots} slots", "offered_rps": serve.offered_load(trace)},
         "radsort": r, "oop": res["oop"],
         "p99_ratio_oop_over_radsort": res["oop"]["p99_ms"] / r["p99_ms"],
     }

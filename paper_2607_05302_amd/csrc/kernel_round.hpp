@@ -385,8 +385,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             const K k = lk[p];
             const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
             const uint64_t pos = (uint64_t)p + dt[d].x;
-            a.Tk[pos] = k;
-            if constexpr (VB != 0) a.Tv[pos] = lv[p];
+            if (pos < a.n) {
+                a.Tk[pos] = k;
+                if constexpr (VB != 0) a.Tv[pos] = lv[p];
+            } else {  // never for consistent digit starts
+                raise_error(a.err, kErrBounds);
+            }
         }
     } else {
         // ---- block draws ----------------------------------------------------------------

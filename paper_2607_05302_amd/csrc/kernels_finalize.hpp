@@ -159,7 +159,8 @@ __global__ void k_fin_rank(const uint32_t* __restrict__ nxt, const uint32_t* __r
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npi;
          p += gridDim.x * blockDim.x) {
         const uint32_t l = V[p] < npi ? V[p] : p;
-        const uint32_t ln = nxt[l] & ~kGarbage;
+        uint32_t ln = nxt[l] & ~kGarbage;
+        if (ln >= npi) ln = l;  // never for a permutation
         const uint32_t len = ln == l ? 1u : O[ln] + 1u;
         rank[p] = p == l ? 0u : len - O[p];
         clen[p] = len;
@@ -483,6 +484,10 @@ __global__ __launch_bounds__(NT) void k_fin_compact(FinArgs<KB, VB> a, const uin
             const uint64_t pos = p0 + i;
             const uint32_t jb = (uint32_t)((pos >> log2b) - j0), off = (uint32_t)pos & (b - 1);
             if (i < cnt && off < bL[jb]) {
+                if (bG[jb] > pos) {  // never for a consistent P
+                    raise_error(a.err, kErrBounds);
+                    continue;
+                }
                 const uint64_t dst = pos - bG[jb];
                 a.Ak[dst] = rk[k];
                 if constexpr (VB != 0) a.Av[dst] = rv[k];

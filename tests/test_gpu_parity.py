@@ -274,3 +274,19 @@ def test_structured_u64_2e30(dist):
     assert bool(seen.all())
     del seen
     assert bool((orig[vals.long()] == keys).all())
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_shared_launch_forms_at_scale(kb):
+    """RADSORT_F_SHARED (one workgroup per tile, claimed in order; dynamic
+    compaction) on 2^26 elements, for Radsort and the baseline, against the oracle."""
+    n = 1 << 26
+    say(f"shared 2^26 kb={kb}")
+    keys = workloads.uniform(0x5EED0006 + kb, n, kb)
+    vals = np.arange(n, dtype=np.uint32)
+    ok, ov = oracle.radsort(keys, vals, 256, kb, 1024)
+    for fn in (radsort.sort_, radsort.oop_sort_):
+        dk, dv = to_dev(keys), to_dev(vals)
+        fn(dk, dv, check=True, shared=True)
+        assert np.array_equal(from_dev(dk, kb).astype(np.uint64), ok), fn.__name__
+        assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov), fn.__name__
