@@ -7,7 +7,8 @@ never loads it, and it shares no code with the GPU library.
 Every routine follows the paper "Parallel O(sqrt n) Overhead LSD Radix Sort":
 setup (Alg. 4), sizeOfNextBlock (Alg. 3), sortPhase (Alg. 5), fixupPhase
 (Alg. 6), finalize (Alg. 7), the driver (Alg. 2), the out-of-place round (Alg. 1)
-and the space formula (Sec. 3, Sec. 4).  Keys and payloads cross this binding as
+the space formula (Sec. 3, Sec. 4), truncate (Alg. 8) and the use of the
+permuted representation without finalize (Sec. 4.1).  Keys and payloads cross this binding as
 uint64 arrays; narrower inputs are widened by the caller.
 """
 from __future__ import annotations
@@ -28,7 +29,7 @@ C_FIRST_ERROR = 3
 NCOUNTERS = 10
 COUNTER_NAMES = [
     "rounds", "lemma1_equal", "finalize_copies", "lemma1_violation",
-    "lemma2_violation", "pool_overrun", "finalize_tail_not_in_T",
+    "lemma2_violation", "pool_overrun", "finalize_tail_overwritten",
     "finalize_count_mismatch", "finalize_home_taken",
 ]
 
@@ -75,6 +76,10 @@ def _bind(lib):
         "orc_get_counters": (None, [vp, _U64P]),
         "orc_get_logical": (u64, [vp, _U64P, _U64P]),
         "orc_check_invariant": (ctypes.c_int, [vp]),
+        "orc_truncate": (ctypes.c_int, [vp, u64, ctypes.c_int64]),
+        "orc_truncate_count": (ctypes.c_int, [vp, u64]),
+        "orc_set_logical": (None, [vp, _U64P, _U64P]),
+        "orc_n": (u64, [vp]),
         "orc_oop_lsd": (ctypes.c_int, [_U64P, _U64P, u64, u64, u64, u64]),
         "orc_histograms": (None, [_U64P, u64, u64, u64, _U64P]),
         "orc_extra_bytes": (u64, [u64, u64, u64, u64, u64, u64]),
@@ -117,13 +122,13 @@ class Radsort:
 
     def __init__(self, keys, vals=None, sigma=256, nt=4, b=1024, lib=None):
         self.lib = lib or load()
-        self.n, self.sigma, self.nt, self.b = len(keys), sigma, nt, b
+        self.n0, self.sigma, self.nt, self.b = len(keys), sigma, nt, b
         self.has_vals = vals is not None
-        self._st = self.lib.orc_create(self.n, sigma, nt, b)
+        self._st = self.lib.orc_create(self.n0, sigma, nt, b)
         if not self._st:
             raise MemoryError("oracle state allocation failed")
         k = _u64(keys)
-        v = _u64(vals) if vals is not None else np.zeros(self.n, np.uint64)
+        v = _u64(vals) if vals is not None else np.zeros(self.n0, np.uint64)
         self.lib.orc_load(self._st, _p(k), _p(v))
 
     def close(self):
@@ -153,7 +158,32 @@ class Radsort:
     def finalize(self):
         self.lib.orc_finalize(self._st)
 
+    def truncate(self, i, j):
+        """Alg. 8: element j of logical block i becomes the last datum (j = -1
+        leaves block i empty)."""
+        if self.lib.orc_truncate(self._st, i, j) != 0:
+            raise ValueError(f"truncate({i}, {j}) names no element of the dataset")
+
+    def truncate_count(self, count):
+        """Keeps the first ``count`` elements of the logical sequence."""
+        if self.lib.orc_truncate_count(self._st, count) != 0:
+            raise ValueError(f"count {count} exceeds the dataset ({self.n})")
+
+    def set_logical(self, keys, vals=None):
+        """Overwrites the dataset in logical order through the permuted
+        representation (``vals`` None keeps the payloads)."""
+        k = _u64(keys)
+        v = _u64(vals) if vals is not None else None
+        if len(k) != self.n or (v is not None and len(v) != self.n):
+            raise ValueError("set_logical needs exactly n elements")
+        self.lib.orc_set_logical(self._st, _p(k), _p(v))
+
     # inspection
+    @property
+    def n(self):
+        """Elements in the dataset (smaller than at creation after truncate)."""
+        return int(self.lib.orc_n(self._st))
+
     @property
     def npi(self):
         return int(self.lib.orc_npi(self._st))

@@ -14,6 +14,8 @@
  *   - blockat (Eq. 1), the state table and the data invariant (Sec. 2.1, 2.2).
  *   - setup (Alg. 4), sizeOfNextBlock (Alg. 3), newBucketBlock and sortPhase
  *     (Alg. 5), fixupPhase (Alg. 6), swap and finalize (Alg. 7).
+ *   - truncate (Alg. 8) and use of the permuted representation without
+ *     finalize (Sec. 4.1).
  *   - radixSortStep, the out-of-place round (Alg. 1).
  *   - the space formula of Sec. 3 and the worked overhead numbers of Sec. 4.
  *
@@ -35,6 +37,12 @@
  *   G7  integer keys: unsigned, ascending; digits by shift/mask for power-of-two
  *       alphabets, by division for other alphabets; sigma is the same in every
  *       round even when the top digit has fewer significant bits.
+ *   G13 truncate (Alg. 8) leaves the entries of P after the one it rewrites;
+ *       they name blocks at or beyond the new f and are inactive.  The final block
+ *       may then be full (length b) and is still tracked in P.
+ *   G14 finalize after truncate: the element count is the truncated one, and a
+ *       block of the tail that sits in the A block right after the homes is first
+ *       moved to a free block of T (the tail copies write into that A block).
  *
  * Lemma 1 is asserted in its tight form: when a new output block is drawn during
  * the scan, i_out < i_in, or i_out == i_in and the element just written was the
@@ -304,9 +312,31 @@ void orc_finalize(orc_state *st)
             j_free = j_in;
         }
     }
+    /* G14: after truncate (Alg. 8) A has more blocks than the floor(n/b) homes, and
+     * the block right after the homes may hold a block of the tail, which the tail
+     * copies below would overwrite before reading it.  Move it to a free block of T
+     * first (T holds at most sigma allocated blocks at this point, so one is free). */
+    if (2 * sigma + nb < st->npi) {
+        uint64_t j_s = 2 * sigma + nb, i_s = st->pinv[j_s];
+        if (sigma + nb <= i_s && i_s < st->f) {
+            uint64_t j_t = 0;
+            while (j_t < 2 * sigma && st->pinv[j_t] >= sigma && st->pinv[j_t] < st->f) j_t++;
+            if (j_t == 2 * sigma) {
+                st->counters[ORC_C_FINALIZE_TAIL_OVERWRITTEN]++;
+            } else {
+                uint64_t i_t = st->pinv[j_t];
+                memcpy(blockat(st, j_t), blockat(st, j_s), b * sizeof(orc_elem));
+                st->counters[ORC_C_FINALIZE_COPIES]++;
+                bind(st, i_s, j_t);
+                bind(st, i_t, j_s);
+            }
+        }
+    }
     for (uint64_t i_in = sigma + nb; i_in < st->f; i_in++) {
         uint64_t j_in = st->pi[i_in];
-        if (j_in >= 2 * sigma) st->counters[ORC_C_FINALIZE_TAIL_NOT_IN_T]++;
+        /* the copies below write A[k .. n); a source in A must lie past that range */
+        if (j_in >= 2 * sigma && j_in - 2 * sigma <= nb)
+            st->counters[ORC_C_FINALIZE_TAIL_OVERWRITTEN]++;
         uint64_t l = size_of_next_block(st, i_in, &iP);
         memmove(st->A + k, blockat(st, j_in), l * sizeof(orc_elem));
         st->counters[ORC_C_FINALIZE_COPIES]++;
@@ -314,6 +344,68 @@ void orc_finalize(orc_state *st)
     }
     if (k != st->n) st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
 }
+
+/* ---- truncate (Alg. 8) and writing through the permuted representation (Sec. 4.1) -- */
+
+/* truncate(i, j): element j of logical block i becomes the last datum.  f becomes
+ * i + 1, and the first entry of P whose logical index is at or after i becomes
+ * (i, j + 1); the entries after it name blocks at or beyond the new f, which
+ * sizeOfNextBlock never reaches, so they are left as they are (G13).  j = -1 leaves
+ * block i empty; truncate(sigma, -1) empties the dataset.  The oracle also keeps
+ * the element count n, which finalize and the invariant check use.  Returns 0, or
+ * -1 (state unchanged) when (i, j) does not name an element of the dataset (or
+ * the place before the first element of block i). */
+int orc_truncate(orc_state *st, uint64_t i, int64_t j)
+{
+    if (i < st->sigma || i >= st->f || j < -1) return -1;
+    uint64_t k = 0, iP = 0;
+    for (uint64_t L = st->sigma; L < i; L++) k += size_of_next_block(st, L, &iP);
+    uint64_t len_i = size_of_next_block(st, i, &iP);
+    if (j >= 0 && (uint64_t)j >= len_i) return -1;
+    st->f = i + 1;                                  /* block i is the final block */
+    for (uint64_t e = 0; e < st->sigma; e++) {      /* skip partials before block i */
+        if (i <= st->Pi[e]) {
+            st->Pi[e] = i;
+            st->Pl[e] = (uint64_t)(j + 1);          /* block i ends at element j */
+            break;
+        }
+    }
+    st->n = k + (uint64_t)(j + 1);
+    return 0;
+}
+
+/* Keeps the first `count` elements of the logical sequence: truncate at the block
+ * and offset of element count - 1, found by walking the blocks as sizeOfNextBlock
+ * does (Alg. 3); count = 0 empties the dataset.  Returns -1 if count > n. */
+int orc_truncate_count(orc_state *st, uint64_t count)
+{
+    if (count == 0) return orc_truncate(st, st->sigma, -1);
+    uint64_t k = 0, iP = 0;
+    for (uint64_t L = st->sigma; L < st->f; L++) {
+        uint64_t l = size_of_next_block(st, L, &iP);
+        if (count - 1 < k + l) return orc_truncate(st, L, (int64_t)(count - 1 - k));
+        k += l;
+    }
+    return -1;
+}
+
+/* Overwrites the used elements of the allocated blocks, in logical order, with
+ * keys[0 .. n) and vals[0 .. n) (vals may be NULL: payloads are kept): the
+ * dataset modified in place through the permuted representation (Sec. 4.1). */
+void orc_set_logical(orc_state *st, const uint64_t *keys, const uint64_t *vals)
+{
+    uint64_t k = 0, iP = 0;
+    for (uint64_t i = st->sigma; i < st->f; i++) {
+        orc_elem *p = blockat(st, st->pi[i]);
+        uint64_t l = size_of_next_block(st, i, &iP);
+        for (uint64_t j = 0; j < l && k < st->n; j++, k++) {
+            p[j].key = keys[k];
+            if (vals) p[j].val = vals[k];
+        }
+    }
+}
+
+uint64_t orc_n(const orc_state *st) { return st->n; }
 
 /* ---- the driver (Alg. 2) ----------------------------------------------------------- */
 
@@ -397,10 +489,13 @@ int orc_check_invariant(orc_state *st)
     int have_prev = 0;
     for (uint64_t i = 0; i < sigma; i++) {
         if (st->Pi[i] == npi) continue; /* dummy entry of setup */
-        if (st->Pi[i] < sigma || st->Pi[i] >= st->f || st->Pl[i] >= st->b) return 2;
-        if (have_prev && st->Pi[i] <= prev) return 2;
+        if (st->Pi[i] < sigma || (have_prev && st->Pi[i] <= prev)) return 2;
         prev = st->Pi[i];
         have_prev = 1;
+        if (st->Pi[i] >= st->f) continue; /* left behind by truncate (G13) */
+        /* a partial block holds fewer than b elements; after truncate the final
+         * block may be full (G13) */
+        if (st->Pl[i] > st->b || (st->Pl[i] == st->b && st->Pi[i] != st->f - 1)) return 2;
     }
     /* clause 3: f-1 is a partial block */
     int found = 0;

@@ -20,7 +20,7 @@ enum {
     ORC_C_LEMMA1_VIOLATION = ORC_C_FIRST_ERROR,
     ORC_C_LEMMA2_VIOLATION,
     ORC_C_POOL_OVERRUN,
-    ORC_C_FINALIZE_TAIL_NOT_IN_T,
+    ORC_C_FINALIZE_TAIL_OVERWRITTEN, /* a tail block sat where the tail copies write */
     ORC_C_FINALIZE_COUNT_MISMATCH,
     ORC_C_FINALIZE_HOME_TAKEN,   /* a home already held a placed block */
     ORC_NCOUNTERS
@@ -49,6 +49,10 @@ void orc_get_C(const orc_state *st, uint64_t *out);
 void orc_get_counters(const orc_state *st, uint64_t *out);
 uint64_t orc_get_logical(orc_state *st, uint64_t *keys, uint64_t *vals);
 int orc_check_invariant(orc_state *st);
+int orc_truncate(orc_state *st, uint64_t i, int64_t j);
+int orc_truncate_count(orc_state *st, uint64_t count);
+void orc_set_logical(orc_state *st, const uint64_t *keys, const uint64_t *vals);
+uint64_t orc_n(const orc_state *st);
 
 int orc_oop_lsd(uint64_t *keys, uint64_t *vals, uint64_t n, uint64_t sigma, uint64_t nt,
                 uint64_t rounds);

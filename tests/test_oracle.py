@@ -240,7 +240,7 @@ def test_finalize_copy_bound(dist):
         R.finalize()
         c = R.counters()
         assert c["finalize_copies"] <= 2 * (n // b) + sigma
-        assert c["finalize_tail_not_in_T"] == 0 and c["finalize_count_mismatch"] == 0
+        assert c["finalize_tail_overwritten"] == 0 and c["finalize_count_mismatch"] == 0
         assert c["finalize_home_taken"] == 0
         k, v = R.result()
         assert np.array_equal(v, np.argsort(keys, kind="stable"))

@@ -5,7 +5,9 @@ textual substitution, builds the copy, and runs the pins of test_oracle.py that
 need no GPU (hand trace, library stable sort, closed forms, invariant) against
 it in a child process.  The two literal readings of the garbled lines of the
 paper (Alg. 3 and Alg. 7) are among the mutants: the pins reject them, which is
-why the oracle takes readings G1 and G2.
+why the oracle takes readings G1 and G2.  Mistakes in truncate (Alg. 8) and in
+finalize after truncate (reading G14) are caught by sorting truncated prefixes
+over a four-letter alphabet.
 """
 import os
 import subprocess
@@ -37,6 +39,13 @@ MUTANTS = {
     "free_slot_not_updated": ("i_free = i_out;\n            j_free = j_in;",
                               "(void)0;"),
     "digit_from_low_end": ("uint64_t below = nt - 1 - t;", "uint64_t below = t;"),
+    "truncate_keeps_f": ("st->f = i + 1;                                  /* block i is",
+                         "(void)0;                                        /* block i is"),
+    "truncate_length_off_by_one": ("st->Pl[e] = (uint64_t)(j + 1);",
+                                   "st->Pl[e] = (uint64_t)(j + 2);"),
+    "truncate_entry_after_block": ("if (i <= st->Pi[e]) {", "if (i < st->Pi[e]) {"),
+    "finalize_no_tail_relocation": ("if (2 * sigma + nb < st->npi) {",
+                                    "if (0 && 2 * sigma + nb < st->npi) {"),
 }
 
 CHECK = r'''
@@ -59,6 +68,28 @@ for dist in ["uniform", "equal", "sorted", "zipf", "few"]:
             rk, ro = stable(keys)
             if not (np.array_equal(k, rk) and np.array_equal(v, ro)):
                 fails.append(("final", dist, n, b))
+# truncate (Alg. 8), more rounds and finalize, against numpy on the prefix
+rng = np.random.default_rng(0x7A11)
+for trial in range(1500):
+    n = int(rng.integers(1, 200)); b = int(rng.choice([1, 2, 3, 4, 5, 8, 16]))
+    scale = np.uint64(int(rng.choice([1, 4, 16])))
+    keys = (rng.integers(0, int(rng.integers(1, 5)), size=n).astype(np.uint64) * scale) & np.uint64(63)
+    vals = np.arange(n, dtype=np.uint64)
+    r, c = int(rng.integers(0, 4)), int(rng.integers(0, n + 1))
+    R = oracle.Radsort(keys, vals, 4, 3, b, lib=lib)
+    R.setup()
+    for q in range(r): R.round(2 - q)
+    R.truncate_count(c)
+    for q in range(r, 3): R.round(2 - q)
+    o = np.argsort(keys & np.uint64((1 << (2 * r)) - 1), kind="stable")
+    pk, pv = keys[o][:c], vals[o][:c]
+    o = np.argsort(pk >> np.uint64(2 * r), kind="stable")
+    R.finalize()
+    fk, fv = R.result()
+    if not (np.array_equal(fk, pk[o]) and np.array_equal(fv, pv[o])):
+        fails.append(("truncate", n, b, r, c)); break
+    if any(v for k, v in R.counters().items() if k not in ("rounds", "lemma1_equal", "finalize_copies")):
+        fails.append(("truncate_counters", n, b, r, c)); break
 g = json.load(open(os.path.join(sys.argv[2], "tests", "golden", "hand_trace_n5_b2_sigma2.json")))
 k, v = oracle.radsort(np.array(g["keys"]), np.array(g["vals"]), 2, 1, 2, lib=lib)
 if k.tolist() != g["final"]["keys"] or v.tolist() != g["final"]["vals"]:
