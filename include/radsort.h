@@ -195,9 +195,14 @@ int radsort_state_setup(radsort_state* st, void* stream);
 /* Enqueues the next round (sort phase, Alg. 5, and fixup phase, Alg. 6).  Rounds
  * run t = n_t-1 first; at most n_t rounds per setup. */
 int radsort_state_round(radsort_state* st, void* stream);
-/* Enqueues finalize (Alg. 7): the data ends sorted in keys/payload. */
+/* Enqueues finalize (Alg. 7): the dataset ends in logical order in keys[0 .. c)
+ * and payload[0 .. c), c = radsort_state_count (n unless truncated; the rest of
+ * the arrays is then unspecified).  The state is used up: rounds, finalize,
+ * truncate, restart, the block table and the gather return RADSORT_E_INVALID
+ * until the next setup. */
 int radsort_state_finalize(radsort_state* st, void* stream);
-/* Finalize by the one-workgroup sequential form of Alg. 7 (slow; a test aid). */
+/* Finalize by the one-workgroup sequential form of Alg. 7 (slow; a test aid).
+ * RADSORT_E_UNSUPPORTED after a truncate. */
 int radsort_state_finalize_sequential(radsort_state* st, void* stream);
 /* Waits for the stream and copies the state to host memory: pi (n_pi uint32),
  * P (sigma logical indices and sigma lengths, uint32) and f.  Any of the output
@@ -206,9 +211,47 @@ int radsort_state_read(radsort_state* st, uint32_t* pi, uint32_t* P_idx, uint32_
                        uint32_t* f, void* stream);
 /* Enqueues a gather of the used elements of logical blocks sigma .. f-1 in
  * logical order (data invariant, clause 5) into device arrays keys_out /
- * payload_out of n elements each. */
+ * payload_out of radsort_state_count elements each. */
 int radsort_state_logical(radsort_state* st, void* keys_out, void* payload_out,
                           void* stream);
+
+/* ---- using the sorted data without finalize (Sec. 4.1) ----------------------
+ * Between rounds, and after the last one, the dataset can be read and changed
+ * in place through the permuted representation, cut short (Alg. 8), and sorted
+ * again from the same state, with no finalize and no new setup.  All of these
+ * are enqueued on `stream` and allocate nothing. */
+
+/* Enqueues the block table of the permuted representation into device arrays of
+ * n_pi - sigma uint32 words (either may be NULL, not both): for logical block
+ * L = sigma .. n_pi - 1, phys[L - sigma] is its physical block pi[L] and
+ * len[L - sigma] its used length; unallocated blocks (L >= f) give phys =
+ * 0xFFFFFFFF and len = 0.  The k-th element of the dataset is element o of the
+ * block that holds it (logical order, Sec. 2.2 clause 5); physical block p starts
+ * at element p * b of the scratch planes (radsort_state_planes) if p < 2 sigma,
+ * else at element (p - 2 sigma) * b of the caller's keys/payload (blockat, Eq. 1).
+ * Keys and payloads may be rewritten there in place; the next round, or a
+ * restart, reads what is there. */
+int radsort_state_blocks(radsort_state* st, uint32_t* phys, uint32_t* len, void* stream);
+/* The device addresses of the scratch planes T (keys, and payload or NULL) and
+ * the block size b in elements.  The planes belong to the state. */
+int radsort_state_planes(const radsort_state* st, void** t_keys, void** t_payload,
+                         uint32_t* block_elems);
+/* Elements in the dataset: n after create and setup, fewer after a truncate
+ * (also after the finalize that follows it). */
+int radsort_state_count(const radsort_state* st, uint64_t* count);
+/* truncate (Alg. 8): keeps the first `count` elements of the dataset in its
+ * current logical order (count = 0 empties it).  Allowed after setup and between
+ * rounds; the rounds still to run then sort the shorter dataset, and so does a
+ * later restart.  Enqueues the change of f and P (Alg. 8) and, if rounds remain,
+ * new digit histograms of the dataset, read through the permuted representation,
+ * and the plan of those rounds.  Returns RADSORT_E_INVALID (state unchanged) if
+ * count exceeds radsort_state_count or the state is not set up. */
+int radsort_state_truncate(radsort_state* st, uint64_t count, void* stream);
+/* Starts a new sort of the current contents from the current state (the state
+ * becomes the input of round 0; another n_t rounds may run): for data changed
+ * in place or truncated since the last sort, with no finalize and no setup.
+ * Enqueues the histograms and the plan of all rounds. */
+int radsort_state_restart(radsort_state* st, void* stream);
 /* n_pi, sigma and n_t of the state. */
 int radsort_state_dims(const radsort_state* st, uint32_t* npi, uint32_t* sigma,
                        uint32_t* nt);

@@ -32,6 +32,8 @@ ABI = [
     "radsort_state_finalize", "radsort_state_finalize_sequential", "radsort_state_read",
     "radsort_state_logical", "radsort_state_dims", "radsort_state_destroy",
     "radsort_sort_segments", "radsort_segments_workspace_bytes",
+    "radsort_state_blocks", "radsort_state_planes", "radsort_state_count",
+    "radsort_state_truncate", "radsort_state_restart",
 ]
 SEG_CLASSES = 32
 
@@ -95,6 +97,11 @@ def load(path: str | None = None):
         "radsort_state_logical": (i32, [vp, vp, vp, vp]),
         "radsort_state_dims": (i32, [vp, u32p, u32p, u32p]),
         "radsort_state_destroy": (i32, [vp]),
+        "radsort_state_blocks": (i32, [vp, vp, vp, vp]),
+        "radsort_state_planes": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), u32p]),
+        "radsort_state_count": (i32, [vp, ctypes.POINTER(u64)]),
+        "radsort_state_truncate": (i32, [vp, u64, vp]),
+        "radsort_state_restart": (i32, [vp, vp]),
         "radsort_sort_segments": (i32, [vp, vp, ctypes.POINTER(u64), vp, ctypes.c_uint32, i32, i32,
                                         ctypes.POINTER(SegTuning), op, vp]),
         "radsort_segments_workspace_bytes": (u64, [ctypes.POINTER(u64), ctypes.c_uint32, i32, i32,
@@ -354,11 +361,47 @@ class State:
                    plen.ctypes.data_as(P), f.ctypes.data_as(P), stream=stream)
         return pi, pidx, plen, int(f[0])
 
-    def logical(self, stream=None):
-        """The permuted representation gathered in logical order (new tensors)."""
+    @property
+    def count(self) -> int:
+        """Elements in the dataset (fewer than n after truncate)."""
+        c = ctypes.c_uint64()
+        _check(load().radsort_state_count(self._h, ctypes.byref(c)))
+        return c.value
+
+    def truncate(self, count: int, stream=None):
+        """truncate (Alg. 8): keep the first ``count`` elements in logical order."""
+        self._call("radsort_state_truncate", ctypes.c_uint64(count), stream=stream)
+
+    def restart(self, stream=None):
+        """Sort the current contents again from this state (no finalize, no setup)."""
+        self._call("radsort_state_restart", stream=stream)
+
+    def blocks(self, stream=None):
+        """The block table (phys, len) of logical blocks sigma .. n_pi - 1, as new
+        int32 device tensors holding uint32 values."""
         import torch
-        ok = torch.empty_like(self.keys)
-        ov = torch.empty_like(self.payload) if self.payload is not None else None
+        m = self.npi - self.sigma
+        phys = torch.empty(m, dtype=torch.int32, device=self.keys.device)
+        ln = torch.empty(m, dtype=torch.int32, device=self.keys.device)
+        self._call("radsort_state_blocks", ctypes.c_void_p(phys.data_ptr()),
+                   ctypes.c_void_p(ln.data_ptr()), stream=stream)
+        return phys, ln
+
+    def planes(self):
+        """(device address of T's keys, of T's payload or None, block size b)."""
+        tk, tv, b = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_uint32()
+        _check(load().radsort_state_planes(self._h, ctypes.byref(tk), ctypes.byref(tv),
+                                           ctypes.byref(b)))
+        return tk.value, tv.value, b.value
+
+    def logical(self, stream=None):
+        """The permuted representation gathered in logical order (new tensors of
+        ``count`` elements)."""
+        import torch
+        c = self.count
+        ok = torch.empty(c, dtype=self.keys.dtype, device=self.keys.device)
+        ov = (torch.empty(c, dtype=self.payload.dtype, device=self.payload.device)
+              if self.payload is not None else None)
         self._call("radsort_state_logical", ctypes.c_void_p(ok.data_ptr()),
                    ctypes.c_void_p(ov.data_ptr() if ov is not None else None), stream=stream)
         return ok, ov

@@ -23,6 +23,10 @@
 //      chunk writes only after every chunk whose source its destination
 //      overlaps has loaded.
 //  F3  the blocks in T are copied to the end of A.
+//
+// After truncate (Alg. 8) the same steps apply with n_pi and the A blocks of the
+// original array: the allocated blocks sigma .. f-1 are fewer, F1 leaves the
+// blocks past f alone as unallocated, and F2 reads nothing from them.
 #pragma once
 
 #include "common.hpp"
@@ -427,6 +431,7 @@ __global__ __launch_bounds__(NT) void k_fin_compact(FinArgs<KB, VB> a, const uin
     __shared__ uint32_t bG[MAXB], bL[MAXB];
     const uint32_t tid = threadIdx.x, b = 1u << a.log2b, sigma = a.sigma, log2b = a.log2b;
     const uint64_t total = (a.n >> log2b) << log2b;  // positions of the full A blocks
+    const uint32_t fcur = *a.f;  // blocks at or past f hold no data (after truncate)
     uint32_t c0 = blockIdx.x, step = gridDim.x;
     if constexpr (DYN) {
         __shared__ uint32_t claimed;
@@ -443,9 +448,10 @@ __global__ __launch_bounds__(NT) void k_fin_compact(FinArgs<KB, VB> a, const uin
         const uint32_t nblk = (uint32_t)(((p0 + cnt - 1) >> log2b) - j0 + 1);
         for (uint32_t i = tid; i < nblk; i += NT) {
             uint32_t G, len;
-            gap_before(a.Pidx, a.Plen, gap, sigma, sigma + (uint32_t)(j0 + i), b, G, len);
+            const uint32_t L = sigma + (uint32_t)(j0 + i);
+            gap_before(a.Pidx, a.Plen, gap, sigma, L, b, G, len);
             bG[i] = G;
-            bL[i] = len;
+            bL[i] = L < fcur ? len : 0u;
         }
         __syncthreads();
         if (bG[nblk - 1] == 0) {  // no gap before this chunk: it stays where it is

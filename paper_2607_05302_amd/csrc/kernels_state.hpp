@@ -74,10 +74,13 @@ struct PlanPtrs {
     uint32_t* est;   // [nt][sigma]
 };
 
+// With init = 1 it also writes index 0 (the state after setup); a plan made
+// again for a state that already exists (after truncate, or to sort its contents
+// again) starts at round r0 and leaves P and f of index r0 as they are.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_plan(const uint32_t* __restrict__ hist, uint64_t n,
                                             uint32_t log2b, uint32_t bits, uint32_t nt,
-                                            uint32_t npi, PlanPtrs p)
+                                            uint32_t npi, uint32_t r0, uint32_t init, PlanPtrs p)
 {
     extern __shared__ uint32_t sm[];
     const uint32_t sigma = 1u << bits, b = 1u << log2b, tid = threadIdx.x;
@@ -85,12 +88,14 @@ __global__ __launch_bounds__(NT) void k_plan(const uint32_t* __restrict__ hist, 
     uint32_t* E = sm + sigma;
     uint32_t* tmp = sm + 2 * sigma;
     const uint32_t nb = (uint32_t)(n >> log2b);
-    if (tid == 0) p.f[0] = sigma + nb + 1;
-    for (uint32_t d = tid; d < sigma; d += NT) {
-        p.Pidx[d] = d == 0 ? sigma + nb : npi;     // the input tail, then dummies
-        p.Plen[d] = d == 0 ? (uint32_t)(n & (b - 1)) : 0;
+    if (init) {
+        if (tid == 0) p.f[0] = sigma + nb + 1;
+        for (uint32_t d = tid; d < sigma; d += NT) {
+            p.Pidx[d] = d == 0 ? sigma + nb : npi;     // the input tail, then dummies
+            p.Plen[d] = d == 0 ? (uint32_t)(n & (b - 1)) : 0;
+        }
     }
-    for (uint32_t r = 0; r < nt; r++) {
+    for (uint32_t r = r0; r < nt; r++) {
         const uint32_t* cnt = hist + (nt - 1 - r) * sigma;
         for (uint32_t d = tid; d < sigma; d += NT) {
             C[d] = 1 + (cnt[d] >> log2b);
@@ -180,6 +185,145 @@ __global__ void k_fixup(uint32_t* __restrict__ pi_old, uint32_t* __restrict__ pi
             else hi = mid;
         }
         blen[j] = (lo < sigma && Pidx[lo] == j) ? Plen[lo] : (1u << log2b);
+    }
+}
+
+// ---- the permuted representation without finalize (Sec. 4.1) -------------------
+
+__global__ void k_copy_u32(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                           uint32_t count)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// truncate (Alg. 8) to the first `count` elements of the logical sequence, on the
+// state (P, f, block lengths) of the current round.  One workgroup.
+// The block holding element q = count - 1 is found from P: every block between
+// two partial blocks is full, so with E_e = the elements before partial block
+// Pidx[e] ((Pidx[e] - sigma) b minus the unused room of the partial blocks
+// before it), q lies in the first partial block that ends after it or in one of
+// the full blocks just before that block.  With (i, j) its block and offset, f
+// becomes i + 1 and that entry of P becomes (i, j + 1) (Alg. 8); the entries
+// after it name blocks past the new f and are left alone.  count = 0 gives
+// (sigma, 0): an empty dataset.  Entries at or past f (left by an earlier
+// truncate) and the dummies of setup take no part.  Dynamic LDS: sigma words.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_truncate(uint32_t* __restrict__ Pidx,
+                                                 uint32_t* __restrict__ Plen,
+                                                 uint32_t* __restrict__ f_ptr,
+                                                 uint32_t* __restrict__ blen, uint32_t sigma,
+                                                 uint32_t log2b, uint64_t count,
+                                                 uint32_t* __restrict__ err)
+{
+    extern __shared__ uint32_t gap[];
+    __shared__ uint32_t tmp[NT / 64 + 1];
+    __shared__ uint32_t found, fe, fi, fj;
+    const uint32_t tid = threadIdx.x, b = 1u << log2b, f = *f_ptr;
+    if (tid == 0) found = 0;
+    for (uint32_t e = tid; e < sigma; e += NT) gap[e] = Pidx[e] < f ? b - min(Plen[e], b) : 0u;
+    __syncthreads();
+    block_excl_scan<NT>(gap, sigma, tmp);  // gap[e] = unused room before block Pidx[e]
+    if (count == 0) {
+        if (tid == 0) {
+            fe = 0;
+            fi = sigma;
+            fj = 0;
+            found = 1;
+        }
+    } else {
+        const uint64_t q = count - 1;
+        for (uint32_t e = tid; e < sigma; e += NT) {
+            const uint32_t idx = Pidx[e];
+            if (idx >= f) continue;
+            const uint64_t before = ((uint64_t)(idx - sigma) << log2b) - gap[e];
+            const uint64_t end = before + min(Plen[e], b);
+            // elements through the previous partial block, and the block after it
+            uint64_t prev_end = 0;
+            uint32_t first = sigma;
+            if (e > 0) {
+                const uint32_t pidx = Pidx[e - 1];
+                prev_end = ((uint64_t)(pidx - sigma) << log2b) - gap[e - 1] + min(Plen[e - 1], b);
+                first = pidx + 1;
+            }
+            if (end <= q || (e > 0 && prev_end > q)) continue;  // not the first to pass q
+            fe = e;  // exactly one entry passes
+            if (q >= before) {
+                fi = idx;
+                fj = (uint32_t)(q - before) + 1;
+            } else {  // a full block between the two partial blocks
+                fi = first + (uint32_t)((q - prev_end) >> log2b);
+                fj = (uint32_t)((q - prev_end) & (b - 1)) + 1;
+            }
+            found = 1;
+        }
+    }
+    __syncthreads();  // every read of P is done before the writes
+    if (tid == 0) {
+        if (!found) {  // count past the data: the state is left as it is
+            raise_error(err, kErrBounds);
+        } else {
+            Pidx[fe] = fi;
+            Plen[fe] = fj;
+            *f_ptr = fi + 1;
+            blen[fi] = fj;
+        }
+    }
+}
+
+// Digit histograms of the current contents of a state for rounds r0 .. nt-1 (key
+// positions t = nt-1-r0 .. 0), read through the permuted representation: the
+// used elements of logical blocks sigma .. f-1.  hist[t * sigma + d], zero on
+// entry.  Dynamic LDS: (nt - r0) * sigma words.
+template <int KB, int NT>
+__global__ __launch_bounds__(NT) void k_histograms_blocks(
+    const typename UInt<KB>::T* __restrict__ Ak, const typename UInt<KB>::T* __restrict__ Tk,
+    const uint32_t* __restrict__ pi, const uint32_t* __restrict__ blen,
+    const uint32_t* __restrict__ f_ptr, uint32_t sigma, uint32_t log2b, uint32_t npi,
+    uint32_t bits, uint32_t r0, uint32_t nt, uint32_t* __restrict__ hist, uint32_t* err)
+{
+    using K = typename UInt<KB>::T;
+    extern __shared__ uint32_t h[];
+    const uint32_t rows = nt - r0, words = rows * sigma, mask = sigma - 1, b = 1u << log2b;
+    for (uint32_t i = threadIdx.x; i < words; i += NT) h[i] = 0;
+    __syncthreads();
+    const uint32_t f = min(*f_ptr, npi);
+    for (uint32_t L = sigma + blockIdx.x; L < f; L += gridDim.x) {
+        const uint32_t p = pi[L];
+        if (p >= npi) {  // never for a consistent state
+            if (threadIdx.x == 0) raise_error(err, kErrBounds);
+            continue;
+        }
+        const uint32_t len = min(blen[L], b);
+        const K* src = blockat(Ak, Tk, p, 2 * sigma, log2b);
+        for (uint32_t o = threadIdx.x; o < len; o += NT) {
+            const K x = src[o];
+            for (uint32_t t = 0; t < rows; t++) {  // round nt-1-t sorts shift bits (nt-1-t)
+                const uint32_t d = (uint32_t)(x >> (bits * (nt - 1 - t))) & mask;
+                atomicAdd(&h[t * sigma + d], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < words; i += NT)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// The block table of the permuted representation: for logical block L = sigma ..
+// n_pi - 1, phys[L - sigma] = pi[L] and len[L - sigma] = its used length, or
+// (0xFFFFFFFF, 0) for the unallocated blocks L >= f.
+__global__ void k_block_table(const uint32_t* __restrict__ pi, const uint32_t* __restrict__ blen,
+                              const uint32_t* __restrict__ f_ptr, uint32_t sigma, uint32_t npi,
+                              uint32_t log2b, uint32_t* __restrict__ phys,
+                              uint32_t* __restrict__ len)
+{
+    const uint32_t f = *f_ptr;
+    for (uint32_t L = sigma + blockIdx.x * blockDim.x + threadIdx.x; L < npi;
+         L += gridDim.x * blockDim.x) {
+        const bool used = L < f;
+        if (phys) phys[L - sigma] = used ? pi[L] : 0xFFFFFFFFu;
+        if (len) len[L - sigma] = used ? min(blen[L], 1u << log2b) : 0u;
     }
 }
 

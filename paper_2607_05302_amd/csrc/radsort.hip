@@ -263,6 +263,8 @@ struct radsort_state {
     void* vals = nullptr;
     uint32_t rounds_done = 0;  // rounds since setup
     int cur = 0;               // which pi buffer holds pi
+    uint64_t count = 0;        // elements in the dataset (fewer after truncate)
+    bool truncated = false;
     bool is_setup = false;
     bool dynamic = false;      // launch forms that need no co-residency (shared GPU)
 
@@ -293,11 +295,13 @@ template <int KB> int launch_histograms(const void* keys, const Geo& g, uint32_t
     return RADSORT_OK;
 }
 
-int launch_plan(const Geo& g, const uint32_t* hist, PlanPtrs p, hipStream_t s)
+// The plan of rounds r0 .. nt-1; init = 1 also writes the state after setup.
+int launch_plan(const Geo& g, const uint32_t* hist, PlanPtrs p, hipStream_t s, uint32_t r0 = 0,
+                uint32_t init = 1)
 {
     const uint32_t lds = 4 * (2 * g.sigma + 8);
     hipLaunchKernelGGL(k_plan<256>, dim3(1), dim3(256), lds, s, hist, g.n, g.log2b, g.bits,
-                       g.nt, g.npi, p);
+                       g.nt, g.npi, r0, init, p);
     return RADSORT_OK;
 }
 
@@ -413,7 +417,71 @@ template <int KB, int VB> struct Ops {
         g_timer.mark(kSetupEnd, 0, s);
         st->cur = 0;
         st->rounds_done = 0;
+        st->count = g.n;
+        st->truncated = false;
         st->is_setup = true;
+        return RADSORT_OK;
+    }
+
+    // Histograms of the state's current contents, read through the permuted
+    // representation, and the plan of rounds r0 .. nt-1 from them.  P and f of
+    // index r0 describe the current state.
+    static void replan(radsort_state* st, uint32_t r0, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        uint32_t* hist = st->u32(st->L.hist);
+        launch_fill(hist, (uint64_t)g.nt * g.sigma, 0, s);
+        const uint32_t rows = g.nt - r0;
+        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(g.npi - g.sigma, 1024));
+        hipLaunchKernelGGL((k_histograms_blocks<KB, 256>), dim3(grid), dim3(256),
+                           4 * rows * g.sigma, s, (const K*)st->keys,
+                           (const K*)(st->ws + st->L.Tk), st->pi(st->cur), st->u32(st->L.blen),
+                           st->u32(st->L.f) + r0, g.sigma, g.log2b, g.npi, g.bits, r0, g.nt, hist,
+                           st->err());
+        launch_plan(g, hist, st->plan(), s, r0, 0);
+    }
+
+    // truncate (Alg. 8) between rounds, then the plan of the rounds still to run
+    static int truncate(radsort_state* st, uint64_t count, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        const uint32_t r = st->rounds_done;
+        hipLaunchKernelGGL(k_truncate<256>, dim3(1), dim3(256), 4 * g.sigma, s,
+                           st->u32(st->L.Pidx) + r * g.sigma, st->u32(st->L.Plen) + r * g.sigma,
+                           st->u32(st->L.f) + r, st->u32(st->L.blen), g.sigma, g.log2b, count,
+                           st->err());
+        st->count = count;
+        st->truncated = true;
+        if (r < g.nt) replan(st, r, s);
+        return RADSORT_OK;
+    }
+
+    // a new sort of the current contents: the state becomes the input of round 0
+    static int restart(radsort_state* st, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        const uint32_t r = st->rounds_done;
+        if (r) {
+            hipLaunchKernelGGL(k_copy_u32, dim3((g.sigma + 255) / 256), dim3(256), 0, s,
+                               st->u32(st->L.Pidx), st->u32(st->L.Pidx) + r * g.sigma, g.sigma);
+            hipLaunchKernelGGL(k_copy_u32, dim3((g.sigma + 255) / 256), dim3(256), 0, s,
+                               st->u32(st->L.Plen), st->u32(st->L.Plen) + r * g.sigma, g.sigma);
+            hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, s, st->u32(st->L.f),
+                               st->u32(st->L.f) + r, 1u);
+        }
+        st->rounds_done = 0;
+        replan(st, 0, s);
+        return RADSORT_OK;
+    }
+
+    static int blocks(radsort_state* st, uint32_t* phys, uint32_t* len, hipStream_t s)
+    {
+        const Geo& g = st->g;
+        const uint32_t m = g.npi - g.sigma;
+        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>((m + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_block_table, dim3(grid), dim3(256), 0, s, st->pi(st->cur),
+                           st->u32(st->L.blen), st->u32(st->L.f) + st->rounds_done, g.sigma,
+                           g.npi, g.log2b, phys, len);
         return RADSORT_OK;
     }
 
@@ -602,6 +670,21 @@ template <int KB, int VB> struct DoFinalize {
 };
 template <int KB, int VB> struct DoFinalizeSeq {
     static int run(radsort_state* st, hipStream_t s) { return Ops<KB, VB>::finalize_seq(st, s); }
+};
+template <int KB, int VB> struct DoTruncate {
+    static int run(radsort_state* st, uint64_t count, hipStream_t s)
+    {
+        return Ops<KB, VB>::truncate(st, count, s);
+    }
+};
+template <int KB, int VB> struct DoRestart {
+    static int run(radsort_state* st, hipStream_t s) { return Ops<KB, VB>::restart(st, s); }
+};
+template <int KB, int VB> struct DoBlocks {
+    static int run(radsort_state* st, uint32_t* phys, uint32_t* len, hipStream_t s)
+    {
+        return Ops<KB, VB>::blocks(st, phys, len, s);
+    }
 };
 template <int KB, int VB> struct DoLogical {
     static int run(radsort_state* st, void* k, void* v, hipStream_t s)
@@ -811,6 +894,7 @@ int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_
     st->L = make_layout(g, false);
     st->keys = keys;
     st->vals = payload;
+    st->count = n;
     if (opts && opts->workspace) {
         if (opts->workspace_bytes < st->L.total) {
             delete st;
@@ -861,6 +945,7 @@ int radsort_state_finalize(radsort_state* st, void* stream)
 int radsort_state_finalize_sequential(radsort_state* st, void* stream)
 {
     if (!st || !st->is_setup) return RADSORT_E_INVALID;
+    if (st->truncated) return RADSORT_E_UNSUPPORTED;
     int rc = dispatch<DoFinalizeSeq>(st->g.kb, st->g.vb, st, (hipStream_t)stream);
     if (rc) return rc;
     RS_HIP(hipGetLastError());
@@ -886,9 +971,54 @@ int radsort_state_read(radsort_state* st, uint32_t* pi, uint32_t* P_idx, uint32_
     return read_err(st, s, nullptr);
 }
 
+int radsort_state_truncate(radsort_state* st, uint64_t count, void* stream)
+{
+    if (!st || !st->is_setup || count > st->count) return RADSORT_E_INVALID;
+    int rc = dispatch<DoTruncate>(st->g.kb, st->g.vb, st, count, (hipStream_t)stream);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    return RADSORT_OK;
+}
+
+int radsort_state_restart(radsort_state* st, void* stream)
+{
+    if (!st || !st->is_setup) return RADSORT_E_INVALID;
+    int rc = dispatch<DoRestart>(st->g.kb, st->g.vb, st, (hipStream_t)stream);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    return RADSORT_OK;
+}
+
+int radsort_state_blocks(radsort_state* st, uint32_t* phys, uint32_t* len, void* stream)
+{
+    if (!st || !st->is_setup || (!phys && !len)) return RADSORT_E_INVALID;
+    int rc = dispatch<DoBlocks>(st->g.kb, st->g.vb, st, phys, len, (hipStream_t)stream);
+    if (rc) return rc;
+    RS_HIP(hipGetLastError());
+    return RADSORT_OK;
+}
+
+int radsort_state_planes(const radsort_state* st, void** t_keys, void** t_payload,
+                         uint32_t* block_elems)
+{
+    if (!st) return RADSORT_E_INVALID;
+    if (t_keys) *t_keys = st->ws + st->L.Tk;
+    if (t_payload) *t_payload = st->g.vb ? (void*)(st->ws + st->L.Tv) : nullptr;
+    if (block_elems) *block_elems = st->g.b;
+    return RADSORT_OK;
+}
+
+int radsort_state_count(const radsort_state* st, uint64_t* count)
+{
+    if (!st || !count) return RADSORT_E_INVALID;
+    *count = st->count;
+    return RADSORT_OK;
+}
+
 int radsort_state_logical(radsort_state* st, void* keys_out, void* payload_out, void* stream)
 {
-    if (!st || (st->g.n && !keys_out) || (st->g.vb && st->g.n && !payload_out))
+    if (!st || !st->is_setup) return RADSORT_E_INVALID;
+    if ((st->count && !keys_out) || (st->g.vb && st->count && !payload_out))
         return RADSORT_E_INVALID;
     int rc = dispatch<DoLogical>(st->g.kb, st->g.vb, st, keys_out, payload_out,
                                  (hipStream_t)stream);
