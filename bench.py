@@ -91,9 +91,12 @@ def main():
     ap.add_argument("--no-oop", action="store_true", help="skip the out-of-place baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["single", "segments", "serving"], default="single",
+    ap.add_argument("--workload", choices=["single", "segments", "serving", "resort"],
+                    default="single",
                     help="segments: 4096 uint32 arrays of log-uniform sizes in one call; "
-                         "serving: a stream of sort requests admitted by memory footprint")
+                         "serving: a stream of sort requests admitted by memory footprint; "
+                         "resort: new keys written in place and sorted again from the same "
+                         "state, without finalize")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests in the trace")
     ap.add_argument("--rate", type=float, default=800.0, help="serving: offered requests/s")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device memory budget")
@@ -118,6 +121,8 @@ def main():
         return bench_segments(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "resort":
+        return bench_resort(args)
     n = 1 << args.log2n
     b, bits, kb, vb = args.block, 8, 4, 4
     dev = torch.device("cuda:0")
@@ -399,6 +404,159 @@ def bench_serving(args):
                                f"{args.slots} slots", "offered_rps": serve.offered_load(trace)},
         "radsort": r, "oop": res["oop"],
         "p99_ratio_oop_over_radsort": res["oop"]["p99_ms"] / r["p99_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+RESORT_SEED = 0x5EED0006
+
+
+def resort_multiplier(step: int) -> int:
+    """The odd multiplier of step `step`: key = payload * m mod 2^32 (as int32)."""
+    m = ((0x9E3779B1 + step * 0x632BE5A6) | 1) & 0xFFFFFFFF
+    return m - (1 << 32) if m >= 1 << 31 else m
+
+
+def bench_resort(args):
+    """Sorting the same data again by new keys without finalize (Sec. 4.1).  n uint32
+    keys with a uint32 index payload are sorted once; then each step gives every
+    element the key payload * m_step mod 2^32, written in place in the permuted
+    representation (one elementwise pass over the key and payload planes of A and
+    T: every element sits at the same slot in both), and sorts the same state
+    again (restart: histograms read through the block table, the plan; then n_t
+    rounds), with no finalize and no setup.  Beside it, the usual way: the same
+    new keys in plain arrays, then a full sort (setup, rounds, finalize).  Also
+    timed once: truncate (Alg. 8) after the last round, truncate between rounds
+    (with the new plan of the rounds left), and finalize of a truncated state."""
+    import numpy as np
+    import torch
+
+    import paper_2607_05302_amd as radsort
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = 1 << args.log2n
+    b, bits, kb, vb = args.block, 8, 4, 4
+    nt = 4
+    keys = workloads.uniform_t(RESORT_SEED, n, 4, dev)
+    vals = torch.arange(n, dtype=torch.int32, device=dev)
+    ws_bytes = radsort.workspace_bytes(n, kb, vb, bits, b)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    st = radsort.State(keys, vals, digit_bits=bits, block_elems=b, workspace=ws)
+    tk, tv, bb = st.planes()
+    tbytes = 2 * st.sigma * bb * 4
+    t_keys = ws[tk - ws.data_ptr():tk - ws.data_ptr() + tbytes].view(torch.int32)
+    t_vals = ws[tv - ws.data_ptr():tv - ws.data_ptr() + tbytes].view(torch.int32)
+    st.setup()
+    for _ in range(nt):
+        st.round()
+
+    def rekey(k, v, step):
+        torch.mul(v, resort_multiplier(step), out=k)
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        return e
+
+    log(f"bench: resort n=2^{args.log2n}, b={b}")
+    phases = {"rekey": [], "restart": [], "rounds": []}
+    times = []
+    step = 0
+    for it in range(args.warmup + args.steps):
+        step += 1
+        e0 = ev()
+        rekey(keys, vals, step)
+        rekey(t_keys, t_vals, step)
+        e1 = ev()
+        st.restart()
+        e2 = ev()
+        for _ in range(nt):
+            st.round()
+        e3 = ev()
+        e3.synchronize()
+        if it >= args.warmup:
+            times.append(e0.elapsed_time(e3))
+            phases["rekey"].append(e0.elapsed_time(e1))
+            phases["restart"].append(e1.elapsed_time(e2))
+            phases["rounds"].append(e2.elapsed_time(e3))
+    st.read()  # device-side error word
+    # check: the dataset in logical order is sorted by its new keys, which are
+    # payload * m mod 2^32, and the payloads are a permutation of 0 .. n-1
+    lk, lv = st.logical()
+    k = lk.to(torch.int64) & 0xFFFFFFFF
+    v = lv.to(torch.int64)
+    m = resort_multiplier(step) & 0xFFFFFFFF
+    ok = bool((k[1:] > k[:-1]).all())
+    ok &= bool(((v * m) & 0xFFFFFFFF == k).all())
+    ok &= bool((torch.bincount(v, minlength=n) == 1).all())
+    del k, v, lk, lv
+
+    # truncate after the last round, truncate between rounds, finalize truncated
+    e0 = ev()
+    st.truncate(n - n // 4)
+    e1 = ev()
+    rekey(keys, vals, step + 1)
+    rekey(t_keys, t_vals, step + 1)
+    st.restart()
+    st.round()
+    st.round()
+    e2 = ev()
+    st.truncate(n // 2)
+    e3 = ev()
+    st.round()
+    st.round()
+    e4 = ev()
+    st.finalize()
+    e5 = ev()
+    e5.synchronize()
+    st.read()
+    c = n // 2
+    k = keys[:c].to(torch.int64) & 0xFFFFFFFF
+    v = vals[:c].to(torch.int64)
+    m = resort_multiplier(step + 1) & 0xFFFFFFFF
+    ok &= bool(((k[1:] >> 16) >= (k[:-1] >> 16)).all())
+    ok &= bool(((v * m) & 0xFFFFFFFF == k).all())
+    del k, v
+    trunc = {"truncate_after_last_round_ms": e0.elapsed_time(e1),
+             "truncate_between_rounds_ms": e2.elapsed_time(e3),
+             "finalize_truncated_ms": e4.elapsed_time(e5)}
+    st.close()
+
+    # the usual way: new keys in the plain arrays, then a full sort
+    keys.copy_(workloads.uniform_t(RESORT_SEED, n, 4, dev))
+    vals.copy_(torch.arange(n, dtype=torch.int32, device=dev))
+    radsort.sort_(keys, vals, digit_bits=bits, block_elems=b, workspace=ws)
+    ftimes = []
+    for it in range(args.warmup + args.steps):
+        e0 = ev()
+        rekey(keys, vals, it + 1)
+        radsort.sort_(keys, vals, digit_bits=bits, block_elems=b, workspace=ws)
+        e1 = ev()
+        e1.synchronize()
+        if it >= args.warmup:
+            ftimes.append(e0.elapsed_time(e1))
+    mean_ms = float(np.mean(times))
+    full_ms = float(np.mean(ftimes))
+    out = {
+        "metric": "keys/s, sorting again without finalize (Sec. 4.1): 2^28 uint32 keys "
+                  "rewritten in place from their uint32 payload, restart + 4 rounds",
+        "value": n / (mean_ms / 1e3), "unit": "keys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mean_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"resort n=2^{args.log2n}: uint32 keys uniform (splitmix64 seed "
+                               f"{RESORT_SEED:#x}) sorted once, then per step key = payload * "
+                               f"m_step mod 2^32 in place and a new sort of the same state; "
+                               f"8-bit digits, b={b}", "n": n, "block_elems": b},
+        "phases_ms": {k: float(np.mean(x)) for k, x in phases.items()},
+        "full_sort_ms_per_step": full_ms,
+        "speedup_vs_full_sort": full_ms / mean_ms,
+        "truncate": trunc,
+        "runs_ms": [round(t, 4) for t in times],
+        "peak_extra_bytes": ws_bytes,
+        "verified": ok,
     }
     print(json.dumps(out), flush=True)
 

@@ -190,10 +190,13 @@ typedef struct radsort_state radsort_state;
 int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_t n,
                          int key_bytes, int payload_bytes, int digit_bits,
                          const radsort_opts* opts);
-/* Enqueues the digit histograms, the closed-form plan and setup (Alg. 4). */
+/* Enqueues setup (Alg. 4): pi, the tail block in T, P and f. */
 int radsort_state_setup(radsort_state* st, void* stream);
-/* Enqueues the next round (sort phase, Alg. 5, and fixup phase, Alg. 6).  Rounds
- * run t = n_t-1 first; at most n_t rounds per setup. */
+/* Enqueues the next round: the digit counts of the round's input (read through
+ * the permuted representation), the closed forms of Alg. 5 and 6 from them (C,
+ * the bucket starts S, the next P and f), the sort phase (Alg. 5) and the fixup
+ * phase (Alg. 6).  Rounds run t = n_t-1 first; at most n_t rounds per setup or
+ * restart. */
 int radsort_state_round(radsort_state* st, void* stream);
 /* Enqueues finalize (Alg. 7): the dataset ends in logical order in keys[0 .. c)
  * and payload[0 .. c), c = radsort_state_count (n unless truncated; the rest of
@@ -242,15 +245,15 @@ int radsort_state_count(const radsort_state* st, uint64_t* count);
 /* truncate (Alg. 8): keeps the first `count` elements of the dataset in its
  * current logical order (count = 0 empties it).  Allowed after setup and between
  * rounds; the rounds still to run then sort the shorter dataset, and so does a
- * later restart.  Enqueues the change of f and P (Alg. 8) and, if rounds remain,
- * new digit histograms of the dataset, read through the permuted representation,
- * and the plan of those rounds.  Returns RADSORT_E_INVALID (state unchanged) if
- * count exceeds radsort_state_count or the state is not set up. */
+ * later restart.  Enqueues one small kernel that finds the block and offset of
+ * element count-1 and changes f and P as Alg. 8 does.  Returns RADSORT_E_INVALID
+ * (state unchanged) if count exceeds radsort_state_count or the state is not set
+ * up. */
 int radsort_state_truncate(radsort_state* st, uint64_t count, void* stream);
 /* Starts a new sort of the current contents from the current state (the state
  * becomes the input of round 0; another n_t rounds may run): for data changed
  * in place or truncated since the last sort, with no finalize and no setup.
- * Enqueues the histograms and the plan of all rounds. */
+ * Enqueues a copy of P and f (2 sigma + 1 words). */
 int radsort_state_restart(radsort_state* st, void* stream);
 /* n_pi, sigma and n_t of the state. */
 int radsort_state_dims(const radsort_state* st, uint32_t* npi, uint32_t* sigma,

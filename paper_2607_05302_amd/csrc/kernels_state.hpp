@@ -74,9 +74,38 @@ struct PlanPtrs {
     uint32_t* est;   // [nt][sigma]
 };
 
-// With init = 1 it also writes index 0 (the state after setup); a plan made
-// again for a state that already exists (after truncate, or to sort its contents
-// again) starts at round r0 and leaves P and f of index r0 as they are.
+// One round of the plan from the digit counts cnt[0..sigma) of its input.  C and
+// E are sigma words of LDS each, tmp NT/64 + 1; est may be null (Radsort itself
+// needs no element starts).  Contains barriers: every thread must call it.
+template <int NT>
+__device__ void plan_round(const uint32_t* __restrict__ cnt, uint32_t sigma, uint32_t log2b,
+                           uint32_t* C, uint32_t* E, uint32_t* tmp, uint32_t* __restrict__ S,
+                           uint32_t* __restrict__ Pidx, uint32_t* __restrict__ Plen,
+                           uint32_t* __restrict__ f, uint32_t* __restrict__ est)
+{
+    const uint32_t b = 1u << log2b, tid = threadIdx.x;
+    for (uint32_t d = tid; d < sigma; d += NT) {
+        C[d] = 1 + (cnt[d] >> log2b);
+        E[d] = cnt[d];
+    }
+    __syncthreads();
+    const uint32_t total = block_excl_scan<NT>(C, sigma, tmp);
+    if (est) block_excl_scan<NT>(E, sigma, tmp);
+    for (uint32_t d = tid; d < sigma; d += NT) {
+        const uint32_t c = 1 + (cnt[d] >> log2b);
+        const uint32_t s = sigma + C[d];
+        S[d] = s;
+        Pidx[d] = s + c - 1;
+        Plen[d] = cnt[d] & (b - 1);
+        if (est) est[d] = E[d];
+    }
+    if (tid == 0) *f = sigma + total;
+    __syncthreads();
+}
+
+// The plan of every round up front from the histograms of all key positions (the
+// out-of-place rounds use it), and with init = 1 index 0: the state after setup
+// (Alg. 4).  r0 = nt writes index 0 alone.  Dynamic LDS: 2 sigma + 8 words.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_plan(const uint32_t* __restrict__ hist, uint64_t n,
                                             uint32_t log2b, uint32_t bits, uint32_t nt,
@@ -84,9 +113,6 @@ __global__ __launch_bounds__(NT) void k_plan(const uint32_t* __restrict__ hist, 
 {
     extern __shared__ uint32_t sm[];
     const uint32_t sigma = 1u << bits, b = 1u << log2b, tid = threadIdx.x;
-    uint32_t* C = sm;
-    uint32_t* E = sm + sigma;
-    uint32_t* tmp = sm + 2 * sigma;
     const uint32_t nb = (uint32_t)(n >> log2b);
     if (init) {
         if (tid == 0) p.f[0] = sigma + nb + 1;
@@ -95,26 +121,25 @@ __global__ __launch_bounds__(NT) void k_plan(const uint32_t* __restrict__ hist, 
             p.Plen[d] = d == 0 ? (uint32_t)(n & (b - 1)) : 0;
         }
     }
-    for (uint32_t r = r0; r < nt; r++) {
-        const uint32_t* cnt = hist + (nt - 1 - r) * sigma;
-        for (uint32_t d = tid; d < sigma; d += NT) {
-            C[d] = 1 + (cnt[d] >> log2b);
-            E[d] = cnt[d];
-        }
-        __syncthreads();
-        uint32_t total = block_excl_scan<NT>(C, sigma, tmp);
-        block_excl_scan<NT>(E, sigma, tmp);
-        for (uint32_t d = tid; d < sigma; d += NT) {
-            uint32_t c = 1 + (cnt[d] >> log2b);
-            uint32_t s = sigma + C[d];
-            p.S[r * sigma + d] = s;
-            p.Pidx[(r + 1) * sigma + d] = s + c - 1;
-            p.Plen[(r + 1) * sigma + d] = cnt[d] & (b - 1);
-            p.est[r * sigma + d] = E[d];
-        }
-        if (tid == 0) p.f[r + 1] = sigma + total;
-        __syncthreads();
-    }
+    for (uint32_t r = r0; r < nt; r++)
+        plan_round<NT>(hist + (nt - 1 - r) * sigma, sigma, log2b, sm, sm + sigma, sm + 2 * sigma,
+                       p.S + r * sigma, p.Pidx + (r + 1) * sigma, p.Plen + (r + 1) * sigma,
+                       p.f + r + 1, p.est + r * sigma);
+}
+
+// The plan of round r alone, from the digit counts of its own input (the totals
+// row of the super-tile scan), just before the round runs: the round's S and
+// the P and f it leaves.  Nothing is planned ahead, so the data may change
+// between rounds (truncate, keys rewritten in place).  Dynamic LDS: 2 sigma + 8.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_plan_round(const uint32_t* __restrict__ cnt,
+                                                  uint32_t log2b, uint32_t bits, uint32_t r,
+                                                  PlanPtrs p)
+{
+    extern __shared__ uint32_t sm[];
+    const uint32_t sigma = 1u << bits;
+    plan_round<NT>(cnt, sigma, log2b, sm, sm + sigma, sm + 2 * sigma, p.S + r * sigma,
+                   p.Pidx + (r + 1) * sigma, p.Plen + (r + 1) * sigma, p.f + r + 1, nullptr);
 }
 
 // setup (Alg. 4): pi = [0..sigma) | 2 sigma .. sigma + f - 2 | sigma .. 2 sigma),
@@ -270,44 +295,6 @@ __global__ __launch_bounds__(NT) void k_truncate(uint32_t* __restrict__ Pidx,
             blen[fi] = fj;
         }
     }
-}
-
-// Digit histograms of the current contents of a state for rounds r0 .. nt-1 (key
-// positions t = nt-1-r0 .. 0), read through the permuted representation: the
-// used elements of logical blocks sigma .. f-1.  hist[t * sigma + d], zero on
-// entry.  Dynamic LDS: (nt - r0) * sigma words.
-template <int KB, int NT>
-__global__ __launch_bounds__(NT) void k_histograms_blocks(
-    const typename UInt<KB>::T* __restrict__ Ak, const typename UInt<KB>::T* __restrict__ Tk,
-    const uint32_t* __restrict__ pi, const uint32_t* __restrict__ blen,
-    const uint32_t* __restrict__ f_ptr, uint32_t sigma, uint32_t log2b, uint32_t npi,
-    uint32_t bits, uint32_t r0, uint32_t nt, uint32_t* __restrict__ hist, uint32_t* err)
-{
-    using K = typename UInt<KB>::T;
-    extern __shared__ uint32_t h[];
-    const uint32_t rows = nt - r0, words = rows * sigma, mask = sigma - 1, b = 1u << log2b;
-    for (uint32_t i = threadIdx.x; i < words; i += NT) h[i] = 0;
-    __syncthreads();
-    const uint32_t f = min(*f_ptr, npi);
-    for (uint32_t L = sigma + blockIdx.x; L < f; L += gridDim.x) {
-        const uint32_t p = pi[L];
-        if (p >= npi) {  // never for a consistent state
-            if (threadIdx.x == 0) raise_error(err, kErrBounds);
-            continue;
-        }
-        const uint32_t len = min(blen[L], b);
-        const K* src = blockat(Ak, Tk, p, 2 * sigma, log2b);
-        for (uint32_t o = threadIdx.x; o < len; o += NT) {
-            const K x = src[o];
-            for (uint32_t t = 0; t < rows; t++) {  // round nt-1-t sorts shift bits (nt-1-t)
-                const uint32_t d = (uint32_t)(x >> (bits * (nt - 1 - t))) & mask;
-                atomicAdd(&h[t * sigma + d], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < words; i += NT)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
 // The block table of the permuted representation: for logical block L = sigma ..

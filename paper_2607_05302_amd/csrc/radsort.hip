@@ -166,9 +166,10 @@ Layout make_layout(const Geo& g, bool oop)
     const uint64_t supers = oop ? g.oop_supers : g.supers;
     const uint64_t agg_bytes = 4ull * g.ring_w * sig;
     const uint64_t done_bytes = align_up(4ull * g.ring_w + 4, 256);  // + the tile counter
-    const uint64_t csum_bytes = align_up(4ull * ((supers + kScanRows - 1) / kScanRows) * sig, 256);
+    // one more row than super-tiles: the column scan leaves the digit totals there
+    const uint64_t csum_bytes = align_up(4ull * ((supers + kScanRows) / kScanRows) * sig, 256);
     L.ring_bytes = agg_bytes + done_bytes + csum_bytes;
-    const uint64_t st_bytes = align_up(4ull * supers * sig, 256);
+    const uint64_t st_bytes = align_up(4ull * (supers + 1) * sig, 256);
     L.fin_bytes = oop ? 0 : finalize_bytes(g);
     L.ring = take(std::max(L.ring_bytes + st_bytes, L.fin_bytes));
     L.agg = L.ring;
@@ -341,21 +342,22 @@ int launch_persistent(const void* kern, uint32_t tiles, uint32_t threads, Args& 
 }
 
 // Digit counts of every super-tile of a round's input, then their column scan:
-// stcnt[u][d] = elements with digit d before super-tile u.
+// stcnt[u][d] = elements with digit d before super-tile u, for u = 0 .. supers;
+// row `supers` (past the input, counted as empty) ends with the digit totals of
+// the round's input.
 template <int KB, bool OOP>
 void launch_super_counts(const Geo& g, const typename UInt<KB>::T* Ak,
                          const typename UInt<KB>::T* Tk, const uint32_t* pi,
                          const uint32_t* blen, const uint32_t* f_in, uint32_t shift,
                          uint32_t* stcnt, uint32_t* csum, uint32_t* err, hipStream_t s)
 {
-    const uint32_t supers = OOP ? g.oop_supers : g.supers;
-    if (!supers) return;
+    const uint32_t rows = (OOP ? g.oop_supers : g.supers) + 1;
     const uint32_t sts_log2 = g.st_log2 + (uint32_t)ilog2(g.E);
-    hipLaunchKernelGGL((k_supertile_counts<KB, OOP, 1024>), dim3(supers), dim3(1024), 0, s, Ak,
-                       Tk, pi, blen, f_in, g.n, shift, g.bits, g.log2b, g.npi, sts_log2, stcnt,
-                       csum, err);
-    hipLaunchKernelGGL(k_column_scan<256>, dim3((supers + kScanRows - 1) / kScanRows), dim3(256),
-                       0, s, stcnt, csum, supers, g.sigma);
+    hipLaunchKernelGGL((k_supertile_counts<KB, OOP, 1024>), dim3(rows), dim3(1024), 0, s, Ak, Tk,
+                       pi, blen, f_in, g.n, shift, g.bits, g.log2b, g.npi, sts_log2, stcnt, csum,
+                       err);
+    hipLaunchKernelGGL(k_column_scan<256>, dim3((rows + kScanRows - 1) / kScanRows), dim3(256), 0,
+                       s, stcnt, csum, rows, g.sigma);
 }
 
 // One workgroup per tile, claimed from a counter (no co-residency needed).
@@ -405,8 +407,8 @@ template <int KB, int VB> struct Ops {
     {
         const Geo& g = st->g;
         g_timer.mark(kStart, 0, s);
-        launch_histograms<KB>(st->keys, g, st->u32(st->L.hist), s);
-        launch_plan(g, st->u32(st->L.hist), st->plan(), s);
+        // P and f after setup; every round is planned from its own digit counts
+        launch_plan(g, nullptr, st->plan(), s, g.nt, 1);
         launch_fill(st->u32(st->L.ctr), g.nt + 8, 0, s);
         uint64_t work = std::max<uint64_t>(g.npi, g.n & (g.b - 1));
         uint32_t grid = (uint32_t)std::min<uint64_t>((work + 255) / 256, 4096);
@@ -423,25 +425,8 @@ template <int KB, int VB> struct Ops {
         return RADSORT_OK;
     }
 
-    // Histograms of the state's current contents, read through the permuted
-    // representation, and the plan of rounds r0 .. nt-1 from them.  P and f of
-    // index r0 describe the current state.
-    static void replan(radsort_state* st, uint32_t r0, hipStream_t s)
-    {
-        const Geo& g = st->g;
-        uint32_t* hist = st->u32(st->L.hist);
-        launch_fill(hist, (uint64_t)g.nt * g.sigma, 0, s);
-        const uint32_t rows = g.nt - r0;
-        const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(g.npi - g.sigma, 1024));
-        hipLaunchKernelGGL((k_histograms_blocks<KB, 256>), dim3(grid), dim3(256),
-                           4 * rows * g.sigma, s, (const K*)st->keys,
-                           (const K*)(st->ws + st->L.Tk), st->pi(st->cur), st->u32(st->L.blen),
-                           st->u32(st->L.f) + r0, g.sigma, g.log2b, g.npi, g.bits, r0, g.nt, hist,
-                           st->err());
-        launch_plan(g, hist, st->plan(), s, r0, 0);
-    }
-
-    // truncate (Alg. 8) between rounds, then the plan of the rounds still to run
+    // truncate (Alg. 8) between rounds; the rounds still to run plan themselves
+    // from the shorter dataset
     static int truncate(radsort_state* st, uint64_t count, hipStream_t s)
     {
         const Geo& g = st->g;
@@ -452,7 +437,6 @@ template <int KB, int VB> struct Ops {
                            st->err());
         st->count = count;
         st->truncated = true;
-        if (r < g.nt) replan(st, r, s);
         return RADSORT_OK;
     }
 
@@ -470,7 +454,6 @@ template <int KB, int VB> struct Ops {
                                st->u32(st->L.f) + r, 1u);
         }
         st->rounds_done = 0;
-        replan(st, 0, s);
         return RADSORT_OK;
     }
 
@@ -517,6 +500,9 @@ template <int KB, int VB> struct Ops {
         g_timer.mark(kCountBegin, r, s);
         launch_super_counts<KB, false>(g, a.Ak, a.Tk, a.pi_old, a.blen, a.f_in, a.shift, stcnt,
                                        st->u32(st->L.csum), a.err, s);
+        hipLaunchKernelGGL(k_plan_round<256>, dim3(1), dim3(256), 4 * (2 * g.sigma + 8), s,
+                           (const uint32_t*)stcnt + (uint64_t)g.supers * g.sigma, g.log2b, g.bits,
+                           r, st->plan());
         g_timer.mark(kRoundBegin, r, s);
         int rc = launch_round_t<KB, VB, false>(g, a, s, st->dynamic);
         if (rc) return rc;
