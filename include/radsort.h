@@ -79,9 +79,10 @@ typedef struct radsort_stats {
     uint32_t error_bits;        /* device error word of the last checked call */
     /* with RADSORT_F_TIMING: milliseconds between HIP events on the call's stream */
     uint32_t timed;             /* 1 when the fields below are valid */
-    float setup_ms;             /* histograms, plan and setup (Alg. 4) */
+    float setup_ms;             /* setup (Alg. 4) */
     float round_ms[RADSORT_MAX_ROUNDS]; /* the sort-round kernel of each round (Alg. 5) */
-    float count_ms[RADSORT_MAX_ROUNDS]; /* each round's super-tile digit counts and their scan */
+    float count_ms[RADSORT_MAX_ROUNDS]; /* each round's super-tile digit counts, their scan
+                                           and the round's plan */
     float fixup_ms;             /* all fixup kernels (Alg. 6) and counter resets */
     float finalize_ms;          /* finalize (Alg. 7); for the baseline: a final copy-back */
     float total_ms;             /* first event to last event */
@@ -91,9 +92,9 @@ typedef struct radsort_stats {
  * radsort_sort_pairs -- sort keys[0..n) in place, ascending and stable, moving
  * payload[i] with keys[i].  Radsort, the driver of Alg. 2: setup (Alg. 4), then
  * for t = n_t-1 .. 0 a sort phase (Alg. 5) and a fixup phase (Alg. 6), then
- * finalize (Alg. 7).  The digit histograms of all key positions are taken up
- * front in one pass (the histogram loop of Alg. 1, run for all positions as the
- * evaluated "generic" variant of Sec. 5 does).
+ * finalize (Alg. 7).  Each round first counts the digits of its own input (the
+ * histogram loop of Alg. 1, per group of tiles) and takes its bucket starts and
+ * the P and f it leaves from those counts by closed forms.
  *   key_bytes      4 or 8 (uint32 / uint64 keys; signed or float keys are not
  *                  handled: the order is that of the unsigned bit patterns)
  *   payload_bytes  0 (payload must be NULL), 4 or 8
@@ -111,7 +112,7 @@ int radsort_sort(void* keys, uint64_t n, int key_bytes, int digit_bits, void* st
 
 /* Workspace bytes radsort_sort_pairs needs for these arguments: the scratch
  * blocks T (2 sigma b elements, Sec. 2.1), two n_pi-entry block permutations,
- * the histograms and per-round closed forms, the look-back status ring and the
+ * the per-round closed forms, the digit counts and look-back status ring and the
  * finalize scratch (which reuses the ring's memory).  0 on invalid arguments. */
 uint64_t radsort_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes,
                                  int digit_bits, const radsort_opts* opts);
@@ -122,7 +123,7 @@ uint64_t radsort_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes,
  * second one of n elements, ping-ponging between the caller's arrays and
  * workspace buffers.  Same arguments, result and ownership as
  * radsort_sort_pairs; it needs n (key_bytes + payload_bytes) extra bytes plus the
- * histogram and look-back state: radsort_oop_workspace_bytes().
+ * digit count and look-back state: radsort_oop_workspace_bytes().
  */
 int radsort_oop_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
                            int payload_bytes, int digit_bits, const radsort_opts* opts,
@@ -161,7 +162,8 @@ uint64_t radsort_segments_workspace_bytes(const uint64_t* offsets, uint32_t nseg
                                           const radsort_opts* opts);
 
 /*
- * radsort_histograms -- the up-front digit histograms alone: counts[t * sigma + c]
+ * radsort_histograms -- the digit histograms of all key positions in one pass
+ * over the keys: counts[t * sigma + c]
  * = number of i with key(keys[i], t) = c, t = 0 the most significant position
  * (the first loop of Alg. 1 for every position).  counts is a device array of
  * n_t * sigma uint32 that the call overwrites.

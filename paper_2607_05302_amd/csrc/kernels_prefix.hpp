@@ -10,6 +10,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "kernels_state.hpp"
 
 namespace rs {
 
@@ -112,9 +113,16 @@ __global__ __launch_bounds__(NT) void k_supertile_counts(
 // In place, for every digit d: cnt[u * sigma + d] becomes sum_{u' < u} cnt[u' * sigma + d].
 // Workgroup c takes the rows of chunk c: it adds up the sums of the earlier
 // chunks, then runs through its own rows.
+//
+// The last row is past the input (its counts are zero), so it ends with the digit
+// totals of the round's input.  With plan != 0 the last workgroup, which wrote
+// that row, then makes the round's plan from it (plan_round: the closed forms of
+// Alg. 5 and 6, and with plan == 2 the element starts of Alg. 1).  Dynamic LDS:
+// 2 sigma + 8 words when planning.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_column_scan(uint32_t* cnt, const uint32_t* csum,
-                                                    uint32_t rows, uint32_t sigma)
+                                                    uint32_t rows, uint32_t sigma,
+                                                    uint32_t log2b, uint32_t plan, PlanPtrs p)
 {
     const uint32_t c = blockIdx.x, r0 = c * kScanRows, r1 = min(rows, r0 + kScanRows);
     for (uint32_t d = threadIdx.x; d < sigma; d += NT) {
@@ -129,6 +137,12 @@ __global__ __launch_bounds__(NT) void k_column_scan(uint32_t* cnt, const uint32_
             if (r0 + i < r1) cnt[(uint64_t)(r0 + i) * sigma + d] = run;
             run += x[i];
         }
+    }
+    if (plan && c + 1 == gridDim.x) {
+        extern __shared__ uint32_t sm[];
+        __syncthreads();  // the totals row was written by this workgroup
+        plan_round<NT>(cnt + (uint64_t)(rows - 1) * sigma, sigma, log2b, sm, sm + sigma,
+                       sm + 2 * sigma, p.S, p.Pidx, p.Plen, p.f, plan == 2 ? p.est : nullptr);
     }
 }
 

@@ -1,5 +1,6 @@
-// State kernels of Radsort: fills, the up-front digit histograms, the per-round
-// plan (closed forms of C, S, P, f), setup (Alg. 4) and fixupPhase (Alg. 6).
+// State kernels of Radsort: fills, the digit histograms of all key positions,
+// the plan of a round (closed forms of C, S, P, f), setup (Alg. 4), fixupPhase
+// (Alg. 6), truncate (Alg. 8) and the block table.
 #pragma once
 
 #include "common.hpp"
@@ -57,8 +58,8 @@ __global__ __launch_bounds__(NT) void k_histograms(const typename UInt<KB>::T* _
     }
 }
 
-// Everything the rounds need that follows from the histograms alone, by the
-// closed forms of Alg. 5 (eager allocation) and Alg. 6:
+// Everything a round needs that follows from the digit counts of its input alone,
+// by the closed forms of Alg. 5 (eager allocation) and Alg. 6:
 //   C[d]   = 1 + floor(cnt_d / b)                     blocks of bucket d
 //   S[d]   = sigma + sum_{d' < d} C[d']               first logical block of d
 //   P[d]   = (S[d] + C[d] - 1, cnt_d mod b)           its partial block
@@ -103,48 +104,10 @@ __device__ void plan_round(const uint32_t* __restrict__ cnt, uint32_t sigma, uin
     __syncthreads();
 }
 
-// The plan of every round up front from the histograms of all key positions (the
-// out-of-place rounds use it), and with init = 1 index 0: the state after setup
-// (Alg. 4).  r0 = nt writes index 0 alone.  Dynamic LDS: 2 sigma + 8 words.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_plan(const uint32_t* __restrict__ hist, uint64_t n,
-                                            uint32_t log2b, uint32_t bits, uint32_t nt,
-                                            uint32_t npi, uint32_t r0, uint32_t init, PlanPtrs p)
-{
-    extern __shared__ uint32_t sm[];
-    const uint32_t sigma = 1u << bits, b = 1u << log2b, tid = threadIdx.x;
-    const uint32_t nb = (uint32_t)(n >> log2b);
-    if (init) {
-        if (tid == 0) p.f[0] = sigma + nb + 1;
-        for (uint32_t d = tid; d < sigma; d += NT) {
-            p.Pidx[d] = d == 0 ? sigma + nb : npi;     // the input tail, then dummies
-            p.Plen[d] = d == 0 ? (uint32_t)(n & (b - 1)) : 0;
-        }
-    }
-    for (uint32_t r = r0; r < nt; r++)
-        plan_round<NT>(hist + (nt - 1 - r) * sigma, sigma, log2b, sm, sm + sigma, sm + 2 * sigma,
-                       p.S + r * sigma, p.Pidx + (r + 1) * sigma, p.Plen + (r + 1) * sigma,
-                       p.f + r + 1, p.est + r * sigma);
-}
-
-// The plan of round r alone, from the digit counts of its own input (the totals
-// row of the super-tile scan), just before the round runs: the round's S and
-// the P and f it leaves.  Nothing is planned ahead, so the data may change
-// between rounds (truncate, keys rewritten in place).  Dynamic LDS: 2 sigma + 8.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_plan_round(const uint32_t* __restrict__ cnt,
-                                                  uint32_t log2b, uint32_t bits, uint32_t r,
-                                                  PlanPtrs p)
-{
-    extern __shared__ uint32_t sm[];
-    const uint32_t sigma = 1u << bits;
-    plan_round<NT>(cnt, sigma, log2b, sm, sm + sigma, sm + 2 * sigma, p.S + r * sigma,
-                   p.Pidx + (r + 1) * sigma, p.Plen + (r + 1) * sigma, p.f + r + 1, nullptr);
-}
-
 // setup (Alg. 4): pi = [0..sigma) | 2 sigma .. sigma + f - 2 | sigma .. 2 sigma),
 // the n mod b tail of A copied to physical block sigma, the other pi buffer
-// cleared to "unset".
+// cleared to "unset", f = sigma + floor(n/b) + 1 and P = the tail block, then
+// dummies (Pidx, Plen, f_out: index 0 of the per-round arrays).
 template <int KB, int VB>
 __global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
                         typename Payload<VB>::T* __restrict__ Av,
@@ -152,12 +115,18 @@ __global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
                         typename Payload<VB>::T* __restrict__ Tv, uint64_t n, uint32_t log2b,
                         uint32_t sigma, uint32_t npi, uint32_t* __restrict__ pi,
                         uint32_t* __restrict__ pi_next, uint32_t* __restrict__ blen,
-                        uint64_t* __restrict__ opened)
+                        uint64_t* __restrict__ opened, uint32_t* __restrict__ Pidx,
+                        uint32_t* __restrict__ Plen, uint32_t* __restrict__ f_out)
 {
     const uint64_t nb = n >> log2b, tail = n - (nb << log2b);
     const uint32_t f = sigma + (uint32_t)nb + 1;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < npi || i < tail;
          i += (uint64_t)gridDim.x * blockDim.x) {
+        if (i < sigma) {
+            Pidx[i] = i == 0 ? f - 1 : npi;  // the input tail, then dummies
+            Plen[i] = i == 0 ? (uint32_t)tail : 0u;
+            if (i == 0) *f_out = f;
+        }
         if (i < npi) {
             uint32_t L = (uint32_t)i, v;
             if (L < sigma) v = L;

@@ -71,7 +71,7 @@ struct Geo {
 
 // Workspace regions (byte offsets), each 256-byte aligned.
 struct Layout {
-    uint64_t Tk, Tv, pi0, pi1, blen, opened, hist, S, Pidx, Plen, f, est, ctr, ring, agg, done,
+    uint64_t Tk, Tv, pi0, pi1, blen, opened, S, Pidx, Plen, f, est, ctr, ring, agg, done,
         csum, stcnt, fin, alt_k, alt_v;
     uint64_t ring_bytes, fin_bytes, total;
 };
@@ -153,7 +153,6 @@ Layout make_layout(const Geo& g, bool oop)
         L.alt_k = take(g.n * g.kb);
         L.alt_v = take(g.n * g.vb);
     }
-    L.hist = take(4 * nt * sig);
     L.S = take(4 * nt * sig);
     L.Pidx = take(4 * (nt + 1) * sig);
     L.Plen = take(4 * (nt + 1) * sig);
@@ -296,16 +295,6 @@ template <int KB> int launch_histograms(const void* keys, const Geo& g, uint32_t
     return RADSORT_OK;
 }
 
-// The plan of rounds r0 .. nt-1; init = 1 also writes the state after setup.
-int launch_plan(const Geo& g, const uint32_t* hist, PlanPtrs p, hipStream_t s, uint32_t r0 = 0,
-                uint32_t init = 1)
-{
-    const uint32_t lds = 4 * (2 * g.sigma + 8);
-    hipLaunchKernelGGL(k_plan<256>, dim3(1), dim3(256), lds, s, hist, g.n, g.log2b, g.bits,
-                       g.nt, g.npi, r0, init, p);
-    return RADSORT_OK;
-}
-
 // Workgroups of `kern` that fit on the device at once (cached per device).
 int resident_capacity(const void* kern, uint32_t threads)
 {
@@ -344,20 +333,25 @@ int launch_persistent(const void* kern, uint32_t tiles, uint32_t threads, Args& 
 // Digit counts of every super-tile of a round's input, then their column scan:
 // stcnt[u][d] = elements with digit d before super-tile u, for u = 0 .. supers;
 // row `supers` (past the input, counted as empty) ends with the digit totals of
-// the round's input.
+// the round's input, from which the scan's last workgroup makes the plan of round
+// r (S[r], P[r+1], f[r+1], and est[r] for the out-of-place round).
 template <int KB, bool OOP>
 void launch_super_counts(const Geo& g, const typename UInt<KB>::T* Ak,
                          const typename UInt<KB>::T* Tk, const uint32_t* pi,
                          const uint32_t* blen, const uint32_t* f_in, uint32_t shift,
-                         uint32_t* stcnt, uint32_t* csum, uint32_t* err, hipStream_t s)
+                         uint32_t* stcnt, uint32_t* csum, uint32_t* err, uint32_t r, PlanPtrs p,
+                         hipStream_t s)
 {
     const uint32_t rows = (OOP ? g.oop_supers : g.supers) + 1;
     const uint32_t sts_log2 = g.st_log2 + (uint32_t)ilog2(g.E);
     hipLaunchKernelGGL((k_supertile_counts<KB, OOP, 1024>), dim3(rows), dim3(1024), 0, s, Ak, Tk,
                        pi, blen, f_in, g.n, shift, g.bits, g.log2b, g.npi, sts_log2, stcnt, csum,
                        err);
-    hipLaunchKernelGGL(k_column_scan<256>, dim3((rows + kScanRows - 1) / kScanRows), dim3(256), 0,
-                       s, stcnt, csum, rows, g.sigma);
+    const uint32_t sig = g.sigma;
+    PlanPtrs pr{p.S + r * sig, p.Pidx + (r + 1) * sig, p.Plen + (r + 1) * sig, p.f + r + 1,
+                p.est + r * sig};
+    hipLaunchKernelGGL(k_column_scan<256>, dim3((rows + kScanRows - 1) / kScanRows), dim3(256),
+                       4 * (2 * sig + 8), s, stcnt, csum, rows, sig, g.log2b, OOP ? 2u : 1u, pr);
 }
 
 // One workgroup per tile, claimed from a counter (no co-residency needed).
@@ -407,15 +401,15 @@ template <int KB, int VB> struct Ops {
     {
         const Geo& g = st->g;
         g_timer.mark(kStart, 0, s);
-        // P and f after setup; every round is planned from its own digit counts
-        launch_plan(g, nullptr, st->plan(), s, g.nt, 1);
+        // every round is planned later from its own digit counts
         launch_fill(st->u32(st->L.ctr), g.nt + 8, 0, s);
         uint64_t work = std::max<uint64_t>(g.npi, g.n & (g.b - 1));
         uint32_t grid = (uint32_t)std::min<uint64_t>((work + 255) / 256, 4096);
         hipLaunchKernelGGL((k_setup<KB, VB>), dim3(grid), dim3(256), 0, s, (K*)st->keys,
                            (V*)st->vals, (K*)(st->ws + st->L.Tk), (V*)(st->ws + st->L.Tv), g.n,
                            g.log2b, g.sigma, g.npi, st->pi(0), st->pi(1), st->u32(st->L.blen),
-                           (uint64_t*)(st->ws + st->L.opened));
+                           (uint64_t*)(st->ws + st->L.opened), st->u32(st->L.Pidx),
+                           st->u32(st->L.Plen), st->u32(st->L.f));
         g_timer.mark(kSetupEnd, 0, s);
         st->cur = 0;
         st->rounds_done = 0;
@@ -499,10 +493,7 @@ template <int KB, int VB> struct Ops {
         launch_fill((uint32_t*)a.agg, st->L.ring_bytes / 4, 0, s);
         g_timer.mark(kCountBegin, r, s);
         launch_super_counts<KB, false>(g, a.Ak, a.Tk, a.pi_old, a.blen, a.f_in, a.shift, stcnt,
-                                       st->u32(st->L.csum), a.err, s);
-        hipLaunchKernelGGL(k_plan_round<256>, dim3(1), dim3(256), 4 * (2 * g.sigma + 8), s,
-                           (const uint32_t*)stcnt + (uint64_t)g.supers * g.sigma, g.log2b, g.bits,
-                           r, st->plan());
+                                       st->u32(st->L.csum), a.err, r, st->plan(), s);
         g_timer.mark(kRoundBegin, r, s);
         int rc = launch_round_t<KB, VB, false>(g, a, s, st->dynamic);
         if (rc) return rc;
@@ -583,12 +574,10 @@ template <int KB, int VB> struct Ops {
     static int oop_sort(void* keys, void* vals, const Geo& g, const Layout& L, uint8_t* ws,
                         bool dyn, hipStream_t s)
     {
-        uint32_t* hist = (uint32_t*)(ws + L.hist);
+        // each round's element starts come from its own digit counts
         PlanPtrs p{(uint32_t*)(ws + L.S), (uint32_t*)(ws + L.Pidx), (uint32_t*)(ws + L.Plen),
                    (uint32_t*)(ws + L.f), (uint32_t*)(ws + L.est)};
         g_timer.mark(kStart, 0, s);
-        launch_histograms<KB>(keys, g, hist, s);
-        launch_plan(g, hist, p, s);
         uint32_t* ctr = (uint32_t*)(ws + L.ctr);
         launch_fill(ctr, g.nt + 8, 0, s);
         g_timer.mark(kSetupEnd, 0, s);
@@ -617,7 +606,8 @@ template <int KB, int VB> struct Ops {
             launch_fill((uint32_t*)a.agg, L.ring_bytes / 4, 0, s);
             g_timer.mark(kCountBegin, r, s);
             launch_super_counts<KB, true>(g, a.Ak, (const K*)nullptr, nullptr, nullptr, nullptr,
-                                          a.shift, stcnt, (uint32_t*)(ws + L.csum), a.err, s);
+                                          a.shift, stcnt, (uint32_t*)(ws + L.csum), a.err, r, p,
+                                          s);
             g_timer.mark(kRoundBegin, r, s);
             int rc = launch_round_t<KB, VB, true>(g, a, s, dyn);
             if (rc) return rc;
