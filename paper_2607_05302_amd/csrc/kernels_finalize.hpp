@@ -278,24 +278,40 @@ __global__ __launch_bounds__(256) void k_fin_save(FinArgs<KB, VB> a, FinArrays f
     }
 }
 
-// Moves one column slice of one job: grid = jobs x (b / kFinCols).
-template <int KB, int VB>
+// VEC consecutive columns of a block, moved by one thread as one wide access
+// (VEC = 4: 16 bytes for 4-byte elements), held in a vector register group.
+template <typename T, int VEC> struct Cols {
+    typedef T type __attribute__((ext_vector_type(VEC)));
+};
+template <typename T> struct Cols<T, 1> {
+    using type = T;
+};
+
+// Moves one column slice of one job: grid = jobs x (b / (kFinCols VEC)).  Thread
+// t of slice y moves columns (y kFinCols + t) VEC .. + VEC - 1 of every block of
+// the job; VEC = 4 needs the caller's arrays 16-byte aligned (b >= 64 keeps every
+// block start aligned then), else VEC = 1.
+template <int KB, int VB, int VEC>
 __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArrays f,
                                                       const uint32_t* rank, const uint32_t* clen,
                                                       const uint32_t* M_ptr)
 {
-    using K = typename UInt<KB>::T;
-    using V = typename Payload<VB>::T;
+    using K = typename Cols<typename UInt<KB>::T, VEC>::type;
+    using V = typename Cols<typename Payload<VB>::T, VEC>::type;
+    using KE = typename UInt<KB>::T;
+    using VE = typename Payload<VB>::T;
     const uint32_t M = min(*M_ptr, a.npi), j = blockIdx.x, b = 1u << a.log2b;
     const uint32_t two_sigma = 2 * a.sigma;
     const uint32_t i0 = j * kFinJob;
     if (i0 >= M) return;
     const uint32_t i1 = min(M, i0 + kFinJob);
-    const uint32_t col = blockIdx.y * kFinCols + threadIdx.x;
-    const bool active = col < b;
+    const uint32_t col = (blockIdx.y * kFinCols + threadIdx.x) * VEC;
+    const bool active = col < b;  // b is a multiple of VEC
     const uint32_t log2b = a.log2b;
-    const K* tk = (const K*)f.temps;
-    const V* tv = (const V*)(f.temps + 2ull * ((a.npi + kFinJob - 1) / kFinJob) * b * KB);
+    // loads in flight per thread: about 512 bytes of registers
+    constexpr uint32_t DEPTH = VEC == 1 ? kFinDepth : (KB + VB <= 8 ? 16u : 8u);
+    const KE* tk = (const KE*)f.temps;
+    const VE* tv = (const VE*)(f.temps + 2ull * ((a.npi + kFinJob - 1) / kFinJob) * b * KB);
     // the job's part of the order array, and the whole cycle of a piece that
     // crosses the job's start or end is read from global memory
     __shared__ uint32_t sord[kFinJob];
@@ -306,8 +322,12 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
     // node ids come from the order array; an id outside [0, n_pi) is clamped to a
     // T block (only possible for a corrupt state, which also raises an error)
     auto safe = [&](uint32_t node) { return node < a.npi ? node : 0u; };
-    auto addr_k = [&](uint32_t node) { return blockat(a.Ak, a.Tk, safe(node), two_sigma, log2b) + col; };
-    auto addr_v = [&](uint32_t node) { return blockat(a.Av, a.Tv, safe(node), two_sigma, log2b) + col; };
+    auto addr_k = [&](uint32_t node) {
+        return (K*)(blockat(a.Ak, a.Tk, safe(node), two_sigma, log2b) + col);
+    };
+    auto addr_v = [&](uint32_t node) {
+        return (V*)(blockat(a.Av, a.Tv, safe(node), two_sigma, log2b) + col);
+    };
 
     uint32_t i = i0;
     while (i < i1) {
@@ -335,19 +355,19 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
                 if constexpr (VB != 0) hv = *addr_v(head & ~kGarbage);
             } else {
                 const uint64_t slot = 2ull * j + (i == i0 ? 0 : 1);
-                hk = tk[(slot << log2b) + col];
-                if constexpr (VB != 0) hv = tv[(slot << log2b) + col];
+                hk = *(const K*)(tk + (slot << log2b) + col);
+                if constexpr (VB != 0) hv = *(const V*)(tv + (slot << log2b) + col);
             }
         }
         // node(x + 1 mod L) <- node(x) for x = rb-1 down to ra+1, in batches
         uint32_t x = rb;  // next source rank + 1
         while (x > ra + 1) {
-            const uint32_t cnt = min(kFinDepth, x - (ra + 1));
-            K bk[kFinDepth];
-            V bv[kFinDepth];
-            uint32_t src[kFinDepth + 1];
+            const uint32_t cnt = min(DEPTH, x - (ra + 1));
+            K bk[DEPTH];
+            V bv[DEPTH];
+            uint32_t src[DEPTH + 1];
 #pragma unroll
-            for (uint32_t u = 0; u < kFinDepth; u++) {
+            for (uint32_t u = 0; u < DEPTH; u++) {
                 if (u < cnt) {
                     src[u] = ord_at(cb + x - 1 - u);
                     if (active && !(src[u] & kGarbage)) {
@@ -357,7 +377,7 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
                 }
             }
 #pragma unroll
-            for (uint32_t u = 0; u < kFinDepth; u++) {
+            for (uint32_t u = 0; u < DEPTH; u++) {
                 if (u < cnt) {
                     const uint32_t rd = x - u;  // destination rank (mod L)
                     const uint32_t dst = ord_at(cb + (rd == L ? 0 : rd)) & ~kGarbage;
@@ -571,9 +591,18 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
                        f.ord, npi);
     const uint32_t jobs = (npi + kFinJob - 1) / kFinJob;
     hipLaunchKernelGGL((k_fin_save<KB, VB>), dim3(jobs), dim3(256), 0, s, a, f, rank, clen, M_ptr);
-    const uint32_t slices = (b + kFinCols - 1) / kFinCols;
-    hipLaunchKernelGGL((k_fin_move<KB, VB>), dim3(jobs, slices), dim3(kFinCols), 0, s, a, f, rank,
-                       clen, M_ptr);
+    // four columns per thread when every block start is 16-byte aligned
+    const bool wide = b >= 64 && (((uintptr_t)a.Ak | (uintptr_t)a.Av | (uintptr_t)a.Tk |
+                                   (uintptr_t)a.Tv | (uintptr_t)f.temps) & 15) == 0;
+    if (wide) {
+        const uint32_t slices = (b + 4 * kFinCols - 1) / (4 * kFinCols);
+        hipLaunchKernelGGL((k_fin_move<KB, VB, 4>), dim3(jobs, slices), dim3(kFinCols), 0, s, a, f,
+                           rank, clen, M_ptr);
+    } else {
+        const uint32_t slices = (b + kFinCols - 1) / kFinCols;
+        hipLaunchKernelGGL((k_fin_move<KB, VB, 1>), dim3(jobs, slices), dim3(kFinCols), 0, s, a, f,
+                           rank, clen, M_ptr);
+    }
     // F2: compaction (gap prefix in f.j0 is free again: rank is dead after the moves)
     uint32_t* gap = Ofin;  // free after k_fin_order
     hipLaunchKernelGGL(k_fin_gaps, dim3(1), dim3(256), 4 * a.sigma, s, a.Pidx, a.Plen, a.sigma,
