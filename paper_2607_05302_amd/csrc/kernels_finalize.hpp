@@ -186,6 +186,124 @@ __global__ void k_fin_order(const uint32_t* __restrict__ nxt, const uint32_t* __
     }
 }
 
+// The whole preparation of F1 (next, the doubling steps, ranks, cycle lengths,
+// the scan of the leaders' cycle lengths and the order array) plus the gap
+// prefix of F2 and the clearing of F2's chunk flags, in one workgroup with the
+// doubling state in LDS, for n_pi <= kFinSmallNodes.  Same results as
+// k_fin_init .. k_fin_order and k_fin_gaps: rank, clen, ord and *M_out (the
+// number of nodes to move) in global memory for k_fin_save / k_fin_move, and
+// gap[0 .. sigma] for F2 / F3.
+constexpr uint32_t kFinSmallNodes = 8192;
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fin_prep_small(
+    const uint32_t* __restrict__ pi, const uint32_t* __restrict__ f_ptr,
+    const uint32_t* __restrict__ Pidx, const uint32_t* __restrict__ Plen, uint32_t sigma,
+    uint32_t log2b, uint32_t npi, uint32_t* __restrict__ rank, uint32_t* __restrict__ clen,
+    uint32_t* __restrict__ ord, uint32_t* __restrict__ M_out, uint32_t* __restrict__ gap,
+    uint32_t* __restrict__ flags, uint64_t nflags, uint32_t* __restrict__ err)
+{
+    constexpr uint32_t PER = kFinSmallNodes / NT;  // nodes per thread
+    __shared__ uint32_t nx[kFinSmallNodes], J[kFinSmallNodes], Vs[kFinSmallNodes],
+        Os[kFinSmallNodes];
+    __shared__ uint32_t tmp[NT / 64 + 1];
+    const uint32_t tid = threadIdx.x, f = *f_ptr;
+    if (npi > kFinSmallNodes) {  // never for a call made by the library
+        if (tid == 0) raise_error(err, kErrBounds);
+        return;
+    }
+    for (uint64_t i = tid; i < nflags; i += NT) flags[i] = 0;
+    // next(pi[L]) = rot(L), garbage bit for unallocated L; J = next, (V, O) = (p, 0)
+    for (uint32_t L = tid; L < npi; L += NT) {
+        uint32_t p = pi[L];
+        if (p >= npi) {  // never for a permutation
+            raise_error(err, kErrBounds);
+            p = L;
+        }
+        const uint32_t to = L + sigma < npi ? L + sigma : L + sigma - npi;
+        nx[p] = to | ((L < sigma || L >= f) ? kGarbage : 0u);
+        J[p] = to;
+        Vs[p] = p;
+        Os[p] = 0;
+    }
+    __syncthreads();
+    // doubling: (V, O) = smallest node within 2^k successors and its distance
+    for (uint32_t w = 1; w < npi; w <<= 1) {
+        uint32_t jn[PER], vn[PER], on[PER];
+#pragma unroll
+        for (uint32_t k = 0; k < PER; k++) {
+            const uint32_t p = tid + k * NT;
+            if (p < npi) {
+                uint32_t q = J[p];
+                if (q >= npi) q = p;
+                uint32_t v = Vs[p], o = Os[p];
+                const uint32_t v2 = Vs[q];
+                if (v2 < v) {
+                    v = v2;
+                    o = Os[q] + w;
+                }
+                jn[k] = J[q];
+                vn[k] = v;
+                on[k] = o;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < PER; k++) {
+            const uint32_t p = tid + k * NT;
+            if (p < npi) {
+                J[p] = jn[k];
+                Vs[p] = vn[k];
+                Os[p] = on[k];
+            }
+        }
+        __syncthreads();
+    }
+    // rank in the cycle (0 at the leader), cycle length, scan input at leaders
+    uint32_t rk[PER], ln[PER];
+#pragma unroll
+    for (uint32_t k = 0; k < PER; k++) {
+        const uint32_t p = tid + k * NT;
+        rk[k] = ln[k] = 0;
+        if (p < npi) {
+            const uint32_t l = Vs[p] < npi ? Vs[p] : p;
+            uint32_t lnx = nx[l] & ~kGarbage;
+            if (lnx >= npi) lnx = l;
+            const uint32_t len = lnx == l ? 1u : Os[lnx] + 1u;
+            rk[k] = p == l ? 0u : len - Os[p];
+            ln[k] = len;
+        }
+    }
+    __syncthreads();  // J is free: it takes the scan input
+#pragma unroll
+    for (uint32_t k = 0; k < PER; k++) {
+        const uint32_t p = tid + k * NT;
+        if (p < npi) {
+            J[p] = (rk[k] == 0 && ln[k] > 1) ? ln[k] : 0u;
+            rank[p] = rk[k];
+            clen[p] = ln[k];
+        }
+    }
+    __syncthreads();
+    const uint32_t M = block_excl_scan<NT>(J, npi, tmp);  // J[leader] = its cycle's base
+#pragma unroll
+    for (uint32_t k = 0; k < PER; k++) {
+        const uint32_t p = tid + k * NT;
+        if (p < npi && ln[k] > 1 && Vs[p] < npi) {
+            const uint32_t at = J[Vs[p]] + rk[k];
+            if (at < npi) ord[at] = p | (nx[p] & kGarbage);
+        }
+    }
+    if (tid == 0) *M_out = M;
+    // F2's gap prefix: unused room of the partial blocks of P before each entry
+    __syncthreads();  // Os is free
+    const uint32_t b = 1u << log2b;
+    for (uint32_t i = tid; i < sigma; i += NT) Os[i] = Pidx[i] < npi ? b - Plen[i] : 0u;
+    __syncthreads();
+    const uint32_t total = block_excl_scan<NT>(Os, sigma, tmp);
+    for (uint32_t i = tid; i < sigma; i += NT) gap[i] = Os[i];
+    if (tid == 0) gap[sigma] = total;
+}
+
 // ---- device exclusive scan of n_pi words (three passes) ------------------------------
 
 __global__ __launch_bounds__(256) void k_scan_tiles(uint32_t* a, uint32_t count, uint32_t* sums)
@@ -567,28 +685,47 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
     const uint32_t npi = a.npi, b = 1u << a.log2b;
     FinArrays f = fin_arrays(a.scratch, npi, a.n, a.spare_pi, a.spare_blen);
     const uint32_t grid = std::min<uint32_t>((npi + 255) / 256, 8192);
-    // F1: cycles
-    uint32_t *J[2] = {f.j0, f.j1}, *Vv[2] = {f.v0, f.v1}, *O[2] = {f.o0, f.o1};
-    hipLaunchKernelGGL(k_fin_init, dim3(grid), dim3(256), 0, s, a.pi, a.f, a.sigma, npi, f.nxt,
-                       J[0], Vv[0], O[0]);
-    int cur = 0;
-    for (uint64_t w = 1; w < npi; w <<= 1) {
-        hipLaunchKernelGGL(k_fin_jump, dim3(grid), dim3(256), 0, s, J[cur], Vv[cur], O[cur],
-                           J[cur ^ 1], Vv[cur ^ 1], O[cur ^ 1], npi, (uint32_t)w);
-        cur ^= 1;
+    uint32_t* rank = f.j0;
+    uint32_t* clen = f.j1;
+    const uint32_t* M_ptr;  // total number of nodes to move
+    uint32_t* gap;          // F2's gap prefix
+    const bool small = npi <= kFinSmallNodes;
+    if (small) {
+        // F1's preparation, F2's gaps and flags in one workgroup
+        hipLaunchKernelGGL(k_fin_prep_small<1024>, dim3(1), dim3(1024), 0, s, a.pi, a.f, a.Pidx,
+                           a.Plen, a.sigma, a.log2b, npi, rank, clen, f.ord, f.sums, f.o0,
+                           f.flags, f.nflags, a.err);
+        M_ptr = f.sums;
+        gap = f.o0;
+    } else {
+        // F1: cycles
+        uint32_t *J[2] = {f.j0, f.j1}, *Vv[2] = {f.v0, f.v1}, *O[2] = {f.o0, f.o1};
+        hipLaunchKernelGGL(k_fin_init, dim3(grid), dim3(256), 0, s, a.pi, a.f, a.sigma, npi,
+                           f.nxt, J[0], Vv[0], O[0]);
+        int cur = 0;
+        for (uint64_t w = 1; w < npi; w <<= 1) {
+            hipLaunchKernelGGL(k_fin_jump, dim3(grid), dim3(256), 0, s, J[cur], Vv[cur], O[cur],
+                               J[cur ^ 1], Vv[cur ^ 1], O[cur ^ 1], npi, (uint32_t)w);
+            cur ^= 1;
+        }
+        uint32_t* V = Vv[cur];
+        uint32_t* Ofin = O[cur];
+        uint32_t* scan = Vv[cur ^ 1];
+        hipLaunchKernelGGL(k_fin_rank, dim3(grid), dim3(256), 0, s, f.nxt, V, Ofin, rank, clen,
+                           scan, npi);
+        fin_scan(scan, npi, f.sums, s);
+        const uint32_t tiles = (npi + kScanTile - 1) / kScanTile;
+        M_ptr = f.sums + tiles;
+        hipLaunchKernelGGL(k_fin_order, dim3(grid), dim3(256), 0, s, f.nxt, V, rank, clen, scan,
+                           f.ord, npi);
+        // F2's gap prefix goes where the doubling state was (free after k_fin_order)
+        gap = Ofin;
+        hipLaunchKernelGGL(k_fin_gaps, dim3(1), dim3(256), 4 * a.sigma, s, a.Pidx, a.Plen,
+                           a.sigma, a.log2b, npi, gap);
+        hipLaunchKernelGGL(k_fill_u32,
+                           dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
+                           dim3(256), 0, s, f.flags, f.nflags, 0u);
     }
-    uint32_t* V = Vv[cur];
-    uint32_t* Ofin = O[cur];
-    uint32_t* rank = J[0];
-    uint32_t* clen = J[1];
-    uint32_t* scan = Vv[cur ^ 1];
-    hipLaunchKernelGGL(k_fin_rank, dim3(grid), dim3(256), 0, s, f.nxt, V, Ofin, rank, clen, scan,
-                       npi);
-    fin_scan(scan, npi, f.sums, s);
-    const uint32_t tiles = (npi + kScanTile - 1) / kScanTile;
-    const uint32_t* M_ptr = f.sums + tiles;  // total number of nodes to move
-    hipLaunchKernelGGL(k_fin_order, dim3(grid), dim3(256), 0, s, f.nxt, V, rank, clen, scan,
-                       f.ord, npi);
     const uint32_t jobs = (npi + kFinJob - 1) / kFinJob;
     hipLaunchKernelGGL((k_fin_save<KB, VB>), dim3(jobs), dim3(256), 0, s, a, f, rank, clen, M_ptr);
     // four columns per thread when every block start is 16-byte aligned
@@ -603,15 +740,10 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
         hipLaunchKernelGGL((k_fin_move<KB, VB, 1>), dim3(jobs, slices), dim3(kFinCols), 0, s, a, f,
                            rank, clen, M_ptr);
     }
-    // F2: compaction (gap prefix in f.j0 is free again: rank is dead after the moves)
-    uint32_t* gap = Ofin;  // free after k_fin_order
-    hipLaunchKernelGGL(k_fin_gaps, dim3(1), dim3(256), 4 * a.sigma, s, a.Pidx, a.Plen, a.sigma,
-                       a.log2b, npi, gap);
+    // F2: compaction
     const uint64_t positions = (a.n >> a.log2b) << a.log2b;
     constexpr int CHUNK = fin_chunk<KB, VB>();
     uint32_t chunks = (uint32_t)((positions + CHUNK - 1) / CHUNK);
-    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
-                       dim3(256), 0, s, f.flags, f.nflags, 0u);
     if (chunks && compact_grid == 0) {
         hipLaunchKernelGGL((k_fin_compact<KB, VB, CHUNK, kCompactThreads, true>), dim3(chunks),
                            dim3(kCompactThreads), 0, s, a, gap, f.flags, chunks);

@@ -22,13 +22,19 @@ constexpr int kMaxSuperBlocks = 2048;  // blocks of one super-tile held in LDS
 // grid; super-tiles past the input write zeros), and csum[c * sigma + d] += the
 // same for chunk c = floor(u / kScanRows) (csum zero on entry).  A super-tile
 // spans at most kMaxSuperBlocks blocks.
+//
+// With plan != 0 (a grid of at most kScanRows workgroups: one chunk) no csum is
+// kept: the last workgroup to finish, found by the counter *done (zero on
+// entry), runs the column scan of k_column_scan itself and then the round's
+// plan (plan == 2: with element starts), so that no scan kernel is needed.
 template <int KB, bool OOP, int NT>
 __global__ __launch_bounds__(NT) void k_supertile_counts(
     const typename UInt<KB>::T* __restrict__ Ak, const typename UInt<KB>::T* __restrict__ Tk,
     const uint32_t* __restrict__ pi, const uint32_t* __restrict__ blen,
     const uint32_t* __restrict__ f_in_p, uint64_t n, uint32_t shift, uint32_t bits,
     uint32_t log2b, uint32_t npi, uint32_t sts_log2, uint32_t* __restrict__ cnt,
-    uint32_t* __restrict__ csum, uint32_t* err)
+    uint32_t* __restrict__ csum, uint32_t* err, uint32_t* __restrict__ done, uint32_t plan,
+    PlanPtrs pp)
 {
     using K = typename UInt<KB>::T;
     constexpr int NW = NT / 64;
@@ -106,8 +112,30 @@ __global__ __launch_bounds__(NT) void k_supertile_counts(
         uint32_t s = 0;
         for (uint32_t c = 0; c < copies; c++) s += h[c * sigma + d];
         cnt[(uint64_t)blockIdx.x * sigma + d] = s;
-        if (s) atomicAdd(csum + (uint64_t)(blockIdx.x / kScanRows) * sigma + d, s);
+        if (s && !plan) atomicAdd(csum + (uint64_t)(blockIdx.x / kScanRows) * sigma + d, s);
     }
+    if (!plan) return;
+    __shared__ uint32_t last;
+    __syncthreads();  // every row of this workgroup is written
+    if (tid == 0) {
+        __threadfence();  // release the rows to the other workgroups
+        last = atomicAdd(done, 1u) == gridDim.x - 1;
+        __threadfence();  // acquire the other workgroups' rows
+    }
+    __syncthreads();
+    if (!last) return;
+    const uint32_t rows = gridDim.x;
+    for (uint32_t d = tid; d < sigma; d += NT) {
+        uint32_t run = 0;
+        for (uint32_t u = 0; u < rows; u++) {
+            const uint32_t x = cnt[(uint64_t)u * sigma + d];
+            cnt[(uint64_t)u * sigma + d] = run;
+            run += x;
+        }
+    }
+    __syncthreads();  // the totals row is written by this workgroup; h is free
+    plan_round<NT>(cnt + (uint64_t)(rows - 1) * sigma, sigma, log2b, h, h + sigma, h + 2 * sigma,
+                   pp.S, pp.Pidx, pp.Plen, pp.f, plan == 2 ? pp.est : nullptr);
 }
 
 // In place, for every digit d: cnt[u * sigma + d] becomes sum_{u' < u} cnt[u' * sigma + d].

@@ -107,7 +107,8 @@ __device__ void plan_round(const uint32_t* __restrict__ cnt, uint32_t sigma, uin
 // setup (Alg. 4): pi = [0..sigma) | 2 sigma .. sigma + f - 2 | sigma .. 2 sigma),
 // the n mod b tail of A copied to physical block sigma, the other pi buffer
 // cleared to "unset", f = sigma + floor(n/b) + 1 and P = the tail block, then
-// dummies (Pidx, Plen, f_out: index 0 of the per-round arrays).
+// dummies (Pidx, Plen, f_out: index 0 of the per-round arrays); the first
+// round's look-back ring (ring_words words) cleared.
 template <int KB, int VB>
 __global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
                         typename Payload<VB>::T* __restrict__ Av,
@@ -116,8 +117,12 @@ __global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
                         uint32_t sigma, uint32_t npi, uint32_t* __restrict__ pi,
                         uint32_t* __restrict__ pi_next, uint32_t* __restrict__ blen,
                         uint64_t* __restrict__ opened, uint32_t* __restrict__ Pidx,
-                        uint32_t* __restrict__ Plen, uint32_t* __restrict__ f_out)
+                        uint32_t* __restrict__ Plen, uint32_t* __restrict__ f_out,
+                        uint32_t* __restrict__ ring, uint64_t ring_words)
 {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ring_words;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        ring[i] = 0;
     const uint64_t nb = n >> log2b, tail = n - (nb << log2b);
     const uint32_t f = sigma + (uint32_t)nb + 1;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < npi || i < tail;
@@ -154,13 +159,18 @@ __global__ void k_setup(typename UInt<KB>::T* __restrict__ Ak,
 // number of blocks drawn.  Each entry of pi_old is read by the thread that owns
 // it, which then resets it to "unset" for the next round.
 // It also writes the used length of every logical block for the next round:
-// b, or the length recorded in P for the buckets' last blocks.
+// b, or the length recorded in P for the buckets' last blocks, and clears the
+// next round's look-back ring (ring_words words).
 __global__ void k_fixup(uint32_t* __restrict__ pi_old, uint32_t* __restrict__ pi_new,
                         const uint32_t* __restrict__ S, const uint32_t* __restrict__ f_out,
                         const uint32_t* __restrict__ Pidx, const uint32_t* __restrict__ Plen,
                         uint32_t* __restrict__ blen, uint64_t* __restrict__ opened,
-                        uint32_t sigma, uint32_t log2b, uint32_t npi)
+                        uint32_t sigma, uint32_t log2b, uint32_t npi, uint32_t* __restrict__ ring,
+                        uint64_t ring_words)
 {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < ring_words;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        ring[i] = 0;
     const uint32_t c = *f_out - sigma;
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < npi;
          j += gridDim.x * blockDim.x) {

@@ -119,7 +119,12 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     // input slots of a round: at most (floor(n/b) + sigma) blocks of b
     uint64_t slots = (g.nb + g.sigma) << g.log2b;
     g.tiles = (uint32_t)((slots + g.E - 1) / g.E);
-    g.ring_w = std::max<uint32_t>(256u, kRingWords / g.sigma);  // powers of two
+    // ring slots (a power of two): one per tile when the tiles fit, else the cap;
+    // with a slot per tile no slot is ever reused
+    const uint32_t ring_cap = std::max<uint32_t>(256u, kRingWords / g.sigma);
+    uint32_t ring_w = 32;
+    while (ring_w < g.tiles && ring_w < ring_cap) ring_w <<= 1;
+    g.ring_w = ring_w;
     g.ring_log2 = ilog2(g.ring_w);
     g.st_log2 = std::max<uint32_t>(kSuperLog2, g.log2b > (uint32_t)ilog2(g.E)
                                                    ? g.log2b - (uint32_t)ilog2(g.E) : 0u);
@@ -164,7 +169,8 @@ Layout make_layout(const Geo& g, bool oop)
     // Finalize reuses all of it.
     const uint64_t supers = oop ? g.oop_supers : g.supers;
     const uint64_t agg_bytes = 4ull * g.ring_w * sig;
-    const uint64_t done_bytes = align_up(4ull * g.ring_w + 4, 256);  // + the tile counter
+    // + the tile counter of the round kernel and the counter of the counting kernel
+    const uint64_t done_bytes = align_up(4ull * g.ring_w + 8, 256);
     // one more row than super-tiles: the column scan leaves the digit totals there
     const uint64_t csum_bytes = align_up(4ull * ((supers + kScanRows) / kScanRows) * sig, 256);
     L.ring_bytes = agg_bytes + done_bytes + csum_bytes;
@@ -339,19 +345,23 @@ template <int KB, bool OOP>
 void launch_super_counts(const Geo& g, const typename UInt<KB>::T* Ak,
                          const typename UInt<KB>::T* Tk, const uint32_t* pi,
                          const uint32_t* blen, const uint32_t* f_in, uint32_t shift,
-                         uint32_t* stcnt, uint32_t* csum, uint32_t* err, uint32_t r, PlanPtrs p,
-                         hipStream_t s)
+                         uint32_t* stcnt, uint32_t* csum, uint32_t* err, uint32_t* done_ctr,
+                         uint32_t r, PlanPtrs p, hipStream_t s)
 {
     const uint32_t rows = (OOP ? g.oop_supers : g.supers) + 1;
     const uint32_t sts_log2 = g.st_log2 + (uint32_t)ilog2(g.E);
-    hipLaunchKernelGGL((k_supertile_counts<KB, OOP, 1024>), dim3(rows), dim3(1024), 0, s, Ak, Tk,
-                       pi, blen, f_in, g.n, shift, g.bits, g.log2b, g.npi, sts_log2, stcnt, csum,
-                       err);
-    const uint32_t sig = g.sigma;
+    const uint32_t sig = g.sigma, plan = OOP ? 2u : 1u;
     PlanPtrs pr{p.S + r * sig, p.Pidx + (r + 1) * sig, p.Plen + (r + 1) * sig, p.f + r + 1,
                 p.est + r * sig};
-    hipLaunchKernelGGL(k_column_scan<256>, dim3((rows + kScanRows - 1) / kScanRows), dim3(256),
-                       4 * (2 * sig + 8), s, stcnt, csum, rows, sig, g.log2b, OOP ? 2u : 1u, pr);
+    // one chunk of rows: the counting kernel's last workgroup scans and plans
+    const bool fused = rows <= kScanRows;
+    hipLaunchKernelGGL((k_supertile_counts<KB, OOP, 1024>), dim3(rows), dim3(1024), 0, s, Ak, Tk,
+                       pi, blen, f_in, g.n, shift, g.bits, g.log2b, g.npi, sts_log2, stcnt, csum,
+                       err, done_ctr, fused ? plan : 0u, pr);
+    if (!fused)
+        hipLaunchKernelGGL(k_column_scan<256>, dim3((rows + kScanRows - 1) / kScanRows),
+                           dim3(256), 4 * (2 * sig + 8), s, stcnt, csum, rows, sig, g.log2b, plan,
+                           pr);
 }
 
 // One workgroup per tile, claimed from a counter (no co-residency needed).
@@ -409,7 +419,8 @@ template <int KB, int VB> struct Ops {
                            (V*)st->vals, (K*)(st->ws + st->L.Tk), (V*)(st->ws + st->L.Tv), g.n,
                            g.log2b, g.sigma, g.npi, st->pi(0), st->pi(1), st->u32(st->L.blen),
                            (uint64_t*)(st->ws + st->L.opened), st->u32(st->L.Pidx),
-                           st->u32(st->L.Plen), st->u32(st->L.f));
+                           st->u32(st->L.Plen), st->u32(st->L.f), st->u32(st->L.ring),
+                           st->L.ring_bytes / 4);
         g_timer.mark(kSetupEnd, 0, s);
         st->cur = 0;
         st->rounds_done = 0;
@@ -490,10 +501,11 @@ template <int KB, int VB> struct Ops {
         a.st_log2 = g.st_log2;
         uint32_t* stcnt = (uint32_t*)(st->ws + st->L.stcnt);
         a.stbase = stcnt;
-        launch_fill((uint32_t*)a.agg, st->L.ring_bytes / 4, 0, s);
+        // the ring is clear: setup or the previous round's fixup cleared it
         g_timer.mark(kCountBegin, r, s);
         launch_super_counts<KB, false>(g, a.Ak, a.Tk, a.pi_old, a.blen, a.f_in, a.shift, stcnt,
-                                       st->u32(st->L.csum), a.err, r, st->plan(), s);
+                                       st->u32(st->L.csum), a.err, a.tile_ctr + 1, r,
+                                       st->plan(), s);
         g_timer.mark(kRoundBegin, r, s);
         int rc = launch_round_t<KB, VB, false>(g, a, s, st->dynamic);
         if (rc) return rc;
@@ -503,7 +515,8 @@ template <int KB, int VB> struct Ops {
                            st->pi(st->cur ^ 1), a.S, st->u32(st->L.f) + r + 1,
                            st->u32(st->L.Pidx) + (r + 1) * g.sigma,
                            st->u32(st->L.Plen) + (r + 1) * g.sigma, st->u32(st->L.blen),
-                           a.opened, g.sigma, g.log2b, g.npi);
+                           a.opened, g.sigma, g.log2b, g.npi, st->u32(st->L.ring),
+                           st->L.ring_bytes / 4);
         g_timer.mark(kFixupEnd, r, s);
         st->cur ^= 1;
         st->rounds_done++;
@@ -606,8 +619,8 @@ template <int KB, int VB> struct Ops {
             launch_fill((uint32_t*)a.agg, L.ring_bytes / 4, 0, s);
             g_timer.mark(kCountBegin, r, s);
             launch_super_counts<KB, true>(g, a.Ak, (const K*)nullptr, nullptr, nullptr, nullptr,
-                                          a.shift, stcnt, (uint32_t*)(ws + L.csum), a.err, r, p,
-                                          s);
+                                          a.shift, stcnt, (uint32_t*)(ws + L.csum), a.err,
+                                          a.tile_ctr + 1, r, p, s);
             g_timer.mark(kRoundBegin, r, s);
             int rc = launch_round_t<KB, VB, true>(g, a, s, dyn);
             if (rc) return rc;
