@@ -18,6 +18,7 @@
 #include "kernel_round.hpp"
 #include "kernels_prefix.hpp"
 #include "kernels_small.hpp"
+#include "kernels_wg.hpp"
 #include "kernels_finalize.hpp"
 #include "kernels_finalize_seq.hpp"
 
@@ -715,9 +716,11 @@ int read_err(radsort_state* st, hipStream_t s, uint32_t* bits)
 // ---- many arrays at once ---------------------------------------------------------
 
 // Arrays of at most kSmallE<KB, VB> elements are sorted whole in LDS by
-// k_sort_small (one workgroup each, no workspace).  Larger ones run the Radsort
-// steps in the dynamic launch form, spread over kSegLanes streams forked from the
-// caller's stream, each lane with its own workspace.
+// k_sort_small (one workgroup each, no workspace).  Arrays up to wg_max_elems()
+// are sorted by k_radsort_wg, one workgroup per array, all of them in one
+// launch, each workgroup with its own T.  Larger ones run the Radsort steps in
+// the dynamic launch form, spread over kSegLanes streams forked from the caller's
+// stream, each lane with its own workspace.
 constexpr uint32_t kSegLanes = 4;
 template <int KB, int VB> struct SmallCfg {
     static constexpr int WAVES = 8;
@@ -748,9 +751,15 @@ struct SegPlan {
     std::vector<uint32_t> lane;   // lane of each of them
     std::vector<SegChoice> choice;
     uint64_t lane_off[kSegLanes] = {}, lane_bytes[kSegLanes] = {};
+    uint32_t wg_count = 0, wg_slots = 0;  // arrays of the one-workgroup path, workgroups
+    uint64_t wg_off = 0, wg_slot_bytes = 0, wg_list_off = 0;
     uint64_t total = 0;
     bool any_small = false;
 };
+
+// Workgroups of the one-workgroup path (each with its own T); they never wait
+// for each other, so they need not all be resident.
+constexpr uint32_t kWgSlots = 256;
 
 int make_seg_plan(SegPlan& P, const uint64_t* off, uint32_t nseg, int kb, int vb,
                   const radsort_seg_tuning* tuning, const radsort_opts* opts)
@@ -763,6 +772,10 @@ int make_seg_plan(SegPlan& P, const uint64_t* off, uint32_t nseg, int kb, int vb
         if (n <= 1) continue;
         if (n <= se) {
             P.any_small = true;
+            continue;
+        }
+        if (n <= wg_max_elems()) {
+            P.wg_count++;
             continue;
         }
         big.push_back({n, i});
@@ -786,10 +799,18 @@ int make_seg_plan(SegPlan& P, const uint64_t* off, uint32_t nseg, int kb, int vb
         P.lane.push_back(l);
         P.choice.push_back(c);
     }
-    uint64_t o = 256;  // the small kernel's error word
+    uint64_t o = 256;  // error words and the one-workgroup path's claim counter
     for (uint32_t l = 0; l < kSegLanes; l++) {
         P.lane_off[l] = o;
         o = align_up(o + P.lane_bytes[l], 256);
+    }
+    if (P.wg_count) {
+        P.wg_slots = std::min(P.wg_count, kWgSlots);
+        P.wg_slot_bytes = wg_slot_bytes(kb, vb);
+        P.wg_list_off = o;
+        o = align_up(o + 4ull * P.wg_count, 256);
+        P.wg_off = o;
+        o += (uint64_t)P.wg_slots * P.wg_slot_bytes;
     }
     P.total = o;
     return RADSORT_OK;
@@ -834,6 +855,22 @@ template <int KB, int VB> struct DoSmall {
         hipLaunchKernelGGL((k_sort_small<KB, VB, C::WAVES, C::ITEMS>), dim3(nseg),
                            dim3(64 * C::WAVES), 0, s, (typename UInt<KB>::T*)keys,
                            (typename Payload<VB>::T*)vals, offsets_dev, nseg, 8u, nt, err);
+        return RADSORT_OK;
+    }
+};
+
+template <int KB, int VB> struct DoWg {
+    static int run(void* keys, void* vals, const uint64_t* offsets_dev, uint32_t nseg,
+                   const SegPlan& P, uint8_t* ws, uint32_t* claim, uint32_t* err, hipStream_t s)
+    {
+        using C = WgCfg<KB, VB>;
+        uint32_t* list = (uint32_t*)(ws + P.wg_list_off);
+        hipLaunchKernelGGL(k_wg_list, dim3(1), dim3(1024), 0, s, offsets_dev, nseg,
+                           (uint64_t)small_elems(KB, VB), wg_max_elems(), list, P.wg_count);
+        hipLaunchKernelGGL((k_radsort_wg<KB, VB>), dim3(P.wg_slots), dim3(C::NT), 0, s,
+                           (typename UInt<KB>::T*)keys, (typename Payload<VB>::T*)vals,
+                           offsets_dev, nseg, (const uint32_t*)list, P.wg_count, claim,
+                           ws + P.wg_off, P.wg_slot_bytes, err);
         return RADSORT_OK;
     }
 };
@@ -1218,11 +1255,17 @@ int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
         }
         own = true;
     }
-    uint32_t* err_small = (uint32_t*)ws;  // [0]: small arrays, [1 + l]: lane l
-    launch_fill(err_small, 1 + kSegLanes, 0, s);
+    // [0]: small arrays, [1 + l]: lane l, [1 + kSegLanes]: the one-workgroup path,
+    // [2 + kSegLanes]: its claim counter
+    uint32_t* err_small = (uint32_t*)ws;
+    launch_fill(err_small, 3 + kSegLanes, 0, s);
     if (P.any_small) {
         rc = dispatch<DoSmall>(key_bytes, payload_bytes, keys, payload, offsets_dev, nseg,
                                err_small, s);
+    }
+    if (!rc && P.wg_count) {
+        rc = dispatch<DoWg>(key_bytes, payload_bytes, keys, payload, offsets_dev, nseg, P, ws,
+                            err_small + 2 + kSegLanes, err_small + 1 + kSegLanes, s);
     }
     if (!rc && !P.large.empty()) {
         LaneStreams* L = nullptr;
@@ -1254,7 +1297,7 @@ int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
     if (!rc && (check || own)) {
         // every lane's error word and the small kernel's
         uint32_t e = 0;
-        std::vector<uint32_t> words(1 + kSegLanes, 0);
+        std::vector<uint32_t> words(2 + kSegLanes, 0);
         RS_HIP(hipStreamSynchronize(s));
         RS_HIP(hipMemcpy(words.data(), err_small, 4 * words.size(), hipMemcpyDeviceToHost));
         for (uint32_t w : words) e |= w;

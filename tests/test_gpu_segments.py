@@ -104,3 +104,34 @@ def test_segments_graph_replay():
         assert int(junk) == (1 << 20) * ((1 << 20) - 1) // 2
         assert torch.equal(dk, ek), f"keys differ on replay {rep}"
         assert torch.equal(dv, ev), f"payload differs on replay {rep}"
+
+
+# the one-workgroup path takes arrays of 8193 .. WG_MAX elements (4096 + 1 .. for
+# records of 12 bytes or more); larger ones run the Radsort steps on the lanes
+WG_MAX = (4352 - 32) * 1024
+
+
+@pytest.mark.parametrize("kb,vb", [(4, 0), (4, 4), (4, 8), (8, 0), (8, 4), (8, 8)])
+def test_segments_one_workgroup_path(kb, vb):
+    """Every key and payload width through the one-workgroup path, at the sizes
+    that bound it (a block, a tile, several thousand blocks, its largest array)
+    and the first size past it (the lanes)."""
+    sizes = [0, 5, 4096, 4097, 8192, 8193, 9000, 1 << 13 | 1 << 10, (1 << 16) + 3, 70000,
+             (1 << 18) + 11, 1 << 20, 3 * (1 << 20) + 5, WG_MAX, WG_MAX + 1]
+    say(f"one-workgroup path kb={kb} vb={vb}")
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = workloads.uniform(0x5EA + kb + vb, int(offsets[-1]), kb)
+    vals = (np.concatenate([np.arange(s, dtype=NP[vb]) for s in sizes]) if vb else None)
+    dk = to_dev(keys)
+    dv = to_dev(vals) if vb else None
+    radsort.sort_segments_(dk, dv, offsets, check=True)
+    got_k = dk.cpu().numpy().view(NP[kb])
+    got_v = dv.cpu().numpy().view(NP[vb]) if vb else None
+    for i in range(len(sizes)):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        if b - a < 2:
+            continue
+        k, v = oracle.radsort(keys[a:b], vals[a:b] if vb else None, 256, kb, 1024)
+        assert np.array_equal(got_k[a:b].astype(np.uint64), k), (i, sizes[i])
+        if vb:
+            assert np.array_equal(got_v[a:b].astype(np.uint64), v), (i, sizes[i])
