@@ -32,6 +32,13 @@
 // block (so no thread waits for another), then F2 closes the gaps of the
 // partial blocks left to right in batches, then the blocks in T follow.  The
 // same two steps as the multi-kernel finalize, run by one workgroup.
+//
+// Wherever global memory that one thread stored is next loaded or stored by
+// another thread (the tail copy of setup and the first round; one round's
+// scatter and the next round; F1 and F2; one array and the next in the same T),
+// every thread first waits for its own stores to complete, then the workgroup
+// meets at a barrier, then the compute unit's cached lines are dropped
+// (wg_global_handoff).  A barrier alone does not wait for stores.
 #pragma once
 
 #include "common.hpp"
@@ -113,7 +120,9 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
     V* const Tv = (V*)((uint8_t*)Tk + (2ull * sigma << log2b) * KB);
 
     for (;;) {
-        __syncthreads();  // the previous array is done with LDS
+        // the previous array is done with LDS, and its stores to this workgroup's T
+        // have landed before the next array writes there
+        wg_global_handoff();
         if (tid == 0) sh_arr = atomicAdd(claim, 1u);
         __syncthreads();
         const uint32_t ai = sh_arr;
@@ -440,7 +449,9 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
             }
             __syncthreads();
         }
-        __syncthreads();
+        // F1 moved whole blocks, also the unused tails of partial blocks, which F2's
+        // stores (by other threads) overwrite: F1's stores land first
+        wg_global_handoff();
 
         // ---- finalize F2: close the gaps; logical L now sits at physical rot(L) --------
         // gap before L: unused room of the partial blocks of P before it
