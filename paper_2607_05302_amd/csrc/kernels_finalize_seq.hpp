@@ -17,9 +17,17 @@ __device__ void wg_move_down(X* dst, const X* src, uint32_t count, bool overlap)
         uint32_t i = c + threadIdx.x;
         X v{};
         if (i < count) v = src[i];
-        if (overlap) __syncthreads();
+        if (overlap) {
+            // the load must have returned before another thread may overwrite
+            // its element: a barrier alone does not wait for it
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
         if (i < count) dst[i] = v;
-        if (overlap) __syncthreads();
+        if (overlap) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
     }
 }
 

@@ -38,7 +38,9 @@
 // scatter and the next round; F1 and F2; one array and the next in the same T),
 // every thread first waits for its own stores to complete, then the workgroup
 // meets at a barrier, then the compute unit's cached lines are dropped
-// (wg_global_handoff).  A barrier alone does not wait for stores.
+// (wg_global_handoff).  A barrier alone waits for neither stores nor loads, so
+// where a thread loads what another thread overwrites after a barrier (F2's
+// batches), the loads are waited for before it.
 #pragma once
 
 #include "common.hpp"
@@ -484,7 +486,10 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
                     }
                 }
             }
-            __syncthreads();  // the batch is read before any of it is overwritten
+            // the batch is read before any of it is overwritten: a load still in
+            // flight at the barrier could return another thread's later store
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
 #pragma unroll
             for (uint32_t u = 0; u < kWgDepth; u++) {
                 if (u < cntb) {
