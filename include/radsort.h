@@ -61,7 +61,8 @@ typedef struct radsort_opts {
 
 #define RADSORT_MAX_ROUNDS 64
 
-/* Block size and digit width per size class for radsort_sort_segments: an array
+/* Block size and digit width per size class for the arrays of radsort_sort_segments
+ * that run the Radsort steps on streams (those above 4 423 680 elements): an array
  * of n elements takes the first class c with ceil(log2 n) <= max_log2n[c].
  * digit_bits must be 4, 8 or 11 and block_elems a power of two in [64, 65536]. */
 #define RADSORT_SEG_CLASSES 32
@@ -137,13 +138,18 @@ uint64_t radsort_oop_workspace_bytes(uint64_t n, int key_bytes, int payload_byte
  * is elements [offsets[i], offsets[i+1]) of the key plane (and of the payload
  * plane).  Arrays of at most 8192 elements (4096 for records of 12 or more bytes)
  * are each sorted whole in LDS by one workgroup, with 8-bit digits and no
- * workspace.  Larger arrays each run Radsort (Alg. 2: setup, n_t x sortPhase +
- * fixupPhase, finalize), with the block size and digit width of their size class
- * in `tuning` (NULL: b = 2^ceil(log2 sqrt n) in [64, 2048] and 8-bit digits, after
- * the b in Theta(sqrt n) of Sec. 3), in launch forms that need no co-residency,
- * spread over four streams forked from `stream` and joined back to it.
+ * workspace.  Arrays of up to 4 423 680 elements are sorted by Radsort (Alg. 2:
+ * setup, n_t x sortPhase + fixupPhase, finalize) run by one workgroup per array,
+ * all of them in one launch, with 4-bit digits and b = 1024 (each of at most 256
+ * workgroups owns a T of 2 * 16 * 1024 elements in the workspace).  Larger arrays
+ * each run the Radsort steps with the block size and digit width of their size
+ * class in `tuning` (NULL: b = 2^ceil(log2 sqrt n) in [64, 2048] and 8-bit digits,
+ * after the b in Theta(sqrt n) of Sec. 3), in launch forms that need no
+ * co-residency, spread over four streams forked from `stream` and joined back to
+ * it.
  *   offsets      host array of nseg + 1 non-decreasing element offsets
- *   offsets_dev  the same array in device memory (read by the small-array kernel)
+ *   offsets_dev  the same array in device memory (read by the kernels; it must hold
+ *                the same values)
  *   opts         block_elems is ignored; workspace / workspace_bytes as for
  *                radsort_sort_pairs (radsort_segments_workspace_bytes gives the
  *                size; with a caller workspace nothing is allocated, so the call can
