@@ -1,11 +1,14 @@
 """Autotuner of the batched segmented sort: per size class, the block size b and
 the digit width with the shortest measured time on this GPU.
 
-For each class (arrays of 2^k elements, k = lo .. hi) it sorts a batch of such
-arrays (seeded uniform keys, index payload) with every candidate (b, digit bits),
-b in {256 .. 8192} (at most the array size) and digit bits in {4, 8, 11}, and keeps
-the fastest.  Arrays small enough for the one-workgroup LDS sort do not use the
-table.  The result is a JSON table that sort_segments_ loads by default:
+The table serves the arrays that run the Radsort steps on streams: those above
+the one-workgroup path (more than 4 423 680 elements); smaller arrays are sorted
+by the LDS sort or by one workgroup each and do not use it.  For each class
+(arrays of 2^k elements, k = lo .. hi) it sorts a batch of such arrays (seeded
+uniform keys, index payload) with every candidate (b, digit bits), b in
+{256 .. 8192} and digit bits in {4, 8, 11}, and keeps the fastest; the last class
+also covers every larger array.  The result is a JSON table that sort_segments_
+loads by default:
 
     python -m paper_2607_05302_amd.tune --key-bytes 4 --payload-bytes 4
 """
@@ -33,7 +36,7 @@ def load_table(key_bytes: int, payload_bytes: int):
     return [tuple(c) for c in t["classes"]]
 
 
-def tune(key_bytes=4, payload_bytes=4, lo=14, hi=22, elems=1 << 25, reps=3, seed=0x7E57,
+def tune(key_bytes=4, payload_bytes=4, lo=23, hi=26, elems=1 << 27, reps=3, seed=0x7E57,
          log=print):
     import numpy as np
     import torch
@@ -93,9 +96,9 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--key-bytes", type=int, default=4)
     ap.add_argument("--payload-bytes", type=int, default=4)
-    ap.add_argument("--lo", type=int, default=14)
-    ap.add_argument("--hi", type=int, default=22)
-    ap.add_argument("--elems", type=int, default=1 << 25, help="elements per timed batch")
+    ap.add_argument("--lo", type=int, default=23)
+    ap.add_argument("--hi", type=int, default=26)
+    ap.add_argument("--elems", type=int, default=1 << 27, help="elements per timed batch")
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     classes, measured = tune(args.key_bytes, args.payload_bytes, args.lo, args.hi, args.elems)

@@ -47,6 +47,10 @@ def expected(offsets, keys, vals, kb):
 
 
 EDGE = [0, 1, 2, 3, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 20000, 70000]
+# the one-workgroup path takes arrays of 8193 .. WG_MAX elements (4096 + 1 .. for
+# records of 12 bytes or more: n_pi = n / 1024 + 32 <= 4352); larger ones run the
+# Radsort steps on the lanes
+WG_MAX = (4352 - 32) * 1024
 
 
 @pytest.mark.parametrize("kb", [4, 8])
@@ -54,6 +58,8 @@ EDGE = [0, 1, 2, 3, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 20000, 70000
 def test_segments_match_oracle(kb, tuned):
     say(f"segments kb={kb} tuned={tuned}")
     sizes = list(workloads.log_uniform_sizes(0x5E6, 200, 0, 19)) + EDGE
+    if tuned:  # one array past the one-workgroup path: the table's last class takes it
+        sizes.append(WG_MAX + 1000)
     offsets, keys, vals = batch(0x5E7 + kb, sizes, kb)
     tuning = [(13, 128, 4), (16, 512, 8), (32, 1024, 11)] if tuned else None
     dk, dv = to_dev(keys), to_dev(vals)
@@ -106,9 +112,6 @@ def test_segments_graph_replay():
         assert torch.equal(dv, ev), f"payload differs on replay {rep}"
 
 
-# the one-workgroup path takes arrays of 8193 .. WG_MAX elements (4096 + 1 .. for
-# records of 12 bytes or more); larger ones run the Radsort steps on the lanes
-WG_MAX = (4352 - 32) * 1024
 
 
 @pytest.mark.parametrize("kb,vb", [(4, 0), (4, 4), (4, 8), (8, 0), (8, 4), (8, 8)])
@@ -135,3 +138,51 @@ def test_segments_one_workgroup_path(kb, vb):
         assert np.array_equal(got_k[a:b].astype(np.uint64), k), (i, sizes[i])
         if vb:
             assert np.array_equal(got_v[a:b].astype(np.uint64), v), (i, sizes[i])
+
+
+@pytest.mark.parametrize("dist", ["equal", "sorted", "zipf", "few", "low20"])
+def test_segments_one_workgroup_path_structured(dist):
+    """Structured keys through the one-workgroup path: one bucket takes every
+    element (all equal), runs already in order (sorted), heavy skew (Zipf), three
+    values, and rounds whose digits are all zero (low 20 bits)."""
+    kb = 8
+    sizes = [9000, 70000, (1 << 20) + 333, WG_MAX]
+    say(f"one-workgroup path structured {dist}")
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = np.concatenate([workloads.make(dist, 0x5EB + i, s, kb) for i, s in enumerate(sizes)])
+    vals = np.concatenate([np.arange(s, dtype=np.uint32) for s in sizes])
+    dk, dv = to_dev(keys), to_dev(vals)
+    radsort.sort_segments_(dk, dv, offsets, check=True)
+    got_k = dk.cpu().numpy().view(np.uint64)
+    got_v = dv.cpu().numpy().view(np.uint32)
+    for i in range(len(sizes)):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        k, v = oracle.radsort(keys[a:b], vals[a:b], 256, kb, 1024)
+        assert np.array_equal(got_k[a:b], k), (dist, sizes[i])
+        assert np.array_equal(got_v[a:b].astype(np.uint64), v), (dist, sizes[i])
+
+
+def test_segments_one_workgroup_path_repeated():
+    """The same batch sorted ten times in a row, each time from fresh copies: a
+    3 M-element array of 12-byte records (one workgroup for a long time) beside
+    its neighbours in the batch.  A hazard that shows only now and then (a wrong
+    histogram, a block written before it was read) fails one of the calls."""
+    kb, vb = 4, 8
+    sizes = [9000, (1 << 20), 3 * (1 << 20) + 5, 70000]
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    keys = workloads.uniform(0x5EC, int(offsets[-1]), kb)
+    vals = np.concatenate([np.arange(s, dtype=np.uint64) for s in sizes])
+    want = []
+    for i in range(len(sizes)):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        want.append(oracle.radsort(keys[a:b], vals[a:b], 256, kb, 1024))
+    for rep in range(10):
+        say(f"one-workgroup path repeated call {rep}")
+        dk, dv = to_dev(keys), to_dev(vals)
+        radsort.sort_segments_(dk, dv, offsets, check=True)
+        got_k = dk.cpu().numpy().view(np.uint32)
+        got_v = dv.cpu().numpy().view(np.uint64)
+        for i, (k, v) in enumerate(want):
+            a, b = int(offsets[i]), int(offsets[i + 1])
+            assert np.array_equal(got_k[a:b].astype(np.uint64), k), (rep, sizes[i])
+            assert np.array_equal(got_v[a:b], v), (rep, sizes[i])
