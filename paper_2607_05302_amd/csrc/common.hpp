@@ -115,8 +115,10 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 }
 
 // Exclusive prefix sum, in place, of a[0..count) in LDS, by all NT threads of the
-// workgroup.  `tmp` holds NT/64 + 1 words of LDS.  Returns the total to every
-// thread.  Contains barriers: every thread of the workgroup must call it.
+// workgroup.  `tmp` holds NT/64 words of LDS.  Returns the total to every thread.
+// Each thread scans its own run of entries; every wave publishes its total and
+// each thread adds the totals of the waves before its own (no serial pass).
+// Contains barriers: every thread of the workgroup must call it.
 template <int NT>
 __device__ uint32_t block_excl_scan(uint32_t* a, uint32_t count, uint32_t* tmp)
 {
@@ -125,27 +127,23 @@ __device__ uint32_t block_excl_scan(uint32_t* a, uint32_t count, uint32_t* tmp)
     const uint32_t lo = min(count, tid * per), hi = min(count, lo + per);
     uint32_t s = 0;
     for (uint32_t i = lo; i < hi; i++) s += a[i];
-    uint32_t incl = wave_incl_scan(s);
+    const uint32_t incl = wave_incl_scan(s);
     if (lane == 63) tmp[wave] = incl;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < NT / 64; w++) {
-            uint32_t t = tmp[w];
-            tmp[w] = run;
-            run += t;
-        }
-        tmp[NT / 64] = run;
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < NT / 64; w++) {
+        const uint32_t t = tmp[w];
+        before += w < wave ? t : 0u;
+        total += t;
     }
-    __syncthreads();
-    uint32_t run = tmp[wave] + incl - s;
+    uint32_t run = before + incl - s;
     for (uint32_t i = lo; i < hi; i++) {
-        uint32_t t = a[i];
+        const uint32_t t = a[i];
         a[i] = run;
         run += t;
     }
-    uint32_t total = tmp[NT / 64];
-    __syncthreads();
+    __syncthreads();  // the results are visible, and tmp may be written again
     return total;
 }
 

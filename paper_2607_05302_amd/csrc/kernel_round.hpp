@@ -185,6 +185,28 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     auto load_tile = [&](uint32_t t) {
         const uint64_t slot0 = (uint64_t)t * E;
         const uint32_t blk0 = (uint32_t)(slot0 >> log2b);
+        if constexpr (!OOP) {
+            if (b >= (uint32_t)SEG) {
+                // the wave's SEG slots lie in one block: one table lookup, then
+                // loads at fixed offsets from one base
+                const uint64_t ws0 = slot0 + wave * SEG;
+                const uint32_t bi = (uint32_t)(ws0 >> log2b) - blk0;
+                const uint32_t off0 = (uint32_t)ws0 & (b - 1);
+                const uint32_t len = t < ntiles ? blen[bi] : 0u;
+                const uint32_t phys = t < ntiles ? bphys[bi] : 0u;
+                const K* kb = blockat(a.Ak, a.Tk, phys, two_sigma, log2b) + off0 + lane;
+                const V* vb = nullptr;
+                if constexpr (VB != 0) vb = blockat(a.Av, a.Tv, phys, two_sigma, log2b) + off0 + lane;
+#pragma unroll
+                for (int j = 0; j < ITEMS; j++) {
+                    const bool valid = off0 + j * 64 + lane < len;
+                    vld[j] = valid;
+                    kn[j] = valid ? kb[j * 64] : (K)0;
+                    if constexpr (VB != 0) vn[j] = valid ? vb[j * 64] : (V)0;
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
             const uint64_t gs = slot0 + wave * SEG + j * 64 + lane;
