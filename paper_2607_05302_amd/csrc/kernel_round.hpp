@@ -156,25 +156,31 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     else nslots = (uint64_t)(f_in - sigma) << log2b;
     const uint32_t ntiles = (uint32_t)((nslots + E - 1) / E);
 
-    // physical index and used length of the blocks of a tile, into bphys / blen
-    auto block_info = [&](uint32_t t) {
+    // physical index and used length of the blocks of a tile: loaded into
+    // registers (thread i < blocks per tile holds block i), then put in bphys / blen
+    static_assert(MAXBLK <= NT, "one thread per block of a tile");
+    const uint32_t nblk = (E >> log2b) ? (E >> log2b) : 1u;
+    auto block_info_load = [&](uint32_t t, uint32_t& phys, uint32_t& len) {
+        phys = 0;
+        len = 0;
         if constexpr (!OOP) {
-            const uint32_t b0 = (uint32_t)(((uint64_t)t * E) >> log2b);
-            const uint32_t nblk = (E >> log2b) ? (E >> log2b) : 1u;
-            for (uint32_t i = tid; i < nblk; i += NT) {
-                const uint32_t L = sigma + b0 + i;
-                uint32_t phys = 0, len = 0;
-                if (L < f_in) {
-                    phys = a.pi_old[L];
-                    len = min(a.blen[L], b);
-                    if (phys >= a.npi) {  // never for a consistent state; read nothing
-                        raise_error(a.err, kErrBounds);
-                        phys = 0;
-                        len = 0;
-                    }
+            const uint32_t L = sigma + (uint32_t)(((uint64_t)t * E) >> log2b) + tid;
+            if (tid < nblk && L < f_in) {
+                phys = a.pi_old[L];
+                len = min(a.blen[L], b);
+            }
+        }
+    };
+    auto block_info_store = [&](uint32_t phys, uint32_t len) {
+        if constexpr (!OOP) {
+            if (tid < nblk) {
+                if (phys >= a.npi) {  // never for a consistent state; read nothing
+                    raise_error(a.err, kErrBounds);
+                    phys = 0;
+                    len = 0;
                 }
-                bphys[i] = phys;
-                blen[i] = len;
+                bphys[tid] = phys;
+                blen[tid] = len;
             }
         }
     };
@@ -238,7 +244,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
         first_tile = claimed;
         step = ntiles;  // one tile per workgroup
     }
-    block_info(first_tile);
+    {
+        uint32_t phys, len;
+        block_info_load(first_tile, phys, len);
+        block_info_store(phys, len);
+    }
     __syncthreads();
     load_tile(first_tile);
 
@@ -258,22 +268,20 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
         uint64_t* myor = (uint64_t*)lk + wave * SMAX;
         for (uint32_t i = lane; i < SMAX; i += 64) myor[i] = 0;
     }
-    // the next tile's block info: its loads are issued once this tile is staged
-    block_info(tile + step);
+    // the next tile's block info: loaded now, put in LDS when this tile is staged
+    // (its loads are issued after that)
+    uint32_t nx_phys, nx_len;
+    block_info_load(tile + step, nx_phys, nx_len);
 
-    // Reuse of this tile's ring slot (see the look-back words above); the tiles
-    // waited for started W tiles earlier, so the wait almost never polls twice.
+    // Reuse of this tile's ring slot (see the look-back words above): the done
+    // words of the tiles that must have finished are requested now and checked
+    // before this tile publishes its counts; those tiles started W tiles earlier,
+    // so the check almost never polls twice.
+    uint32_t rq = 0, rqend = 0, rv = 0;
     if ((uint64_t)tile > wmask) {
-        const uint32_t q = tile - (uint32_t)wmask - 1;           // tile - W
-        const uint32_t qend = min((q | (mst - 1)) + 1, ntiles);  // end of its super-tile
-        for (uint32_t j = q + tid; j < qend; j += NT) {
-            const uint32_t* w = a.done + (j & wmask);
-            uint32_t spins = 0;
-            while (ld_agent(w) <= j) {
-                if (spin_give_up(++spins, a.err)) break;
-                spin_pause();
-            }
-        }
+        rq = tile - (uint32_t)wmask - 1;                    // tile - W
+        rqend = min((rq | (mst - 1)) + 1, ntiles);          // end of its super-tile
+        if (rq + tid < rqend) rv = ld_agent(a.done + ((rq + tid) & wmask));
     }
 
     // ---- stable rank among equal digits of the wave ----------------------------------
@@ -317,6 +325,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     // Every load of the tile has returned (the payload is not read before staging,
     // so wait for it here): from the counts' publication on, other tiles may
     // reuse the tile's blocks.
+    for (uint32_t j = rq + tid; j < rqend; j += NT) {
+        const uint32_t* w = a.done + (j & wmask);
+        uint32_t v = j == rq + tid ? rv : ld_agent(w), spins = 0;
+        while (v <= j) {
+            if (spin_give_up(++spins, a.err)) break;
+            spin_pause();
+            v = ld_agent(w);
+        }
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
@@ -354,6 +371,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             ls[p] = (uint16_t)(wave * SEG + j * 64 + lane);
         }
     }
+    block_info_store(nx_phys, nx_len);
     __syncthreads();
     // registers are free again: issue the next tile's loads
     load_tile(tile + step);
