@@ -382,6 +382,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
 
     // ---- look back over the super-tile -----------------------------------------------
     for (uint32_t d = tid; d < sigma; d += NT) {
+        // the super-tile's digit start, requested with the first look-back loads
+        const uint32_t sbase = a.stbase[(uint64_t)(tile >> a.st_log2) * sigma + d];
         // sum the counts of tiles st0 .. tile-1, up to kLookbackWin loads at once;
         // while one has not published, poll that one alone
         uint32_t acc = 0, k = tile, spins = 0;
@@ -413,7 +415,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
                 spin_pause();
             }
         }
-        base[d] = a.stbase[(uint64_t)(tile >> a.st_log2) * sigma + d] + acc;
+        base[d] = sbase + acc;
     }
     __syncthreads();
     if (tid == 0) st_agent(a.done + (tile & wmask), tile + 1);
