@@ -140,7 +140,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     __shared__ uint32_t pool[OOP ? 1 : TBL];     // physical blocks of the tile's draws
     __shared__ uint32_t fmask[E / 32], fpref[E / 32];
     __shared__ uint32_t bphys[MAXBLK], blen[MAXBLK];
-    __shared__ uint32_t tmp[2 * (NT / 64) + 2];
+    __shared__ uint32_t tmp[3 * (NT / 64) + 2];
 
     uint16_t* ls = (uint16_t*)uni;               // slot of each staged element
     uint32_t* cnt = uni + E / 2;
@@ -340,23 +340,58 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     // ---- per-digit tile counts (published at once) and wave offsets ------------------
     const uint32_t st0 = tile & ~(mst - 1);  // first tile of this tile's super-tile
     uint32_t* mycnt = a.agg + (uint64_t)(tile & wmask) * sigma;
-    for (uint32_t d = tid; d < sigma; d += NT) {
+    uint32_t total;
+    if constexpr (SMAX <= NT) {
+        // one digit per thread: its count, the scan over the digits and the wave
+        // offsets in one pass
+        const uint32_t d = tid;
         uint32_t run = 0;
+        if (d < sigma) {
 #pragma unroll
-        for (int w = 0; w < WAVES; w++) {
-            const uint32_t c = wh[w * SMAX + d];
-            wh[w * SMAX + d] = run;
-            run += c;
+            for (int w = 0; w < WAVES; w++) {
+                const uint32_t c = wh[w * SMAX + d];
+                wh[w * SMAX + d] = run;
+                run += c;
+            }
+            st_agent(mycnt + d, run | epoch_bit(tile, wlog));
+            cnt[d] = run;
         }
-        st_agent(mycnt + d, run | epoch_bit(tile, wlog));
-        cnt[d] = run;
-        excl[d] = run;
-    }
-    __syncthreads();
-    const uint32_t total = block_excl_scan<NT>(excl, sigma, tmp);
-    for (uint32_t d = tid; d < sigma; d += NT) {
+        const uint32_t incl = wave_incl_scan(run);
+        if (lane == 63) tmp[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0;
+        total = 0;
 #pragma unroll
-        for (int w = 0; w < WAVES; w++) wh[w * SMAX + d] += excl[d];
+        for (uint32_t w = 0; w < NT / 64; w++) {
+            const uint32_t t = tmp[w];
+            before += w < wave ? t : 0u;
+            total += t;
+        }
+        if (d < sigma) {
+            const uint32_t ex = before + incl - run;
+            excl[d] = ex;
+#pragma unroll
+            for (int w = 0; w < WAVES; w++) wh[w * SMAX + d] += ex;
+        }
+    } else {
+        for (uint32_t d = tid; d < sigma; d += NT) {
+            uint32_t run = 0;
+#pragma unroll
+            for (int w = 0; w < WAVES; w++) {
+                const uint32_t c = wh[w * SMAX + d];
+                wh[w * SMAX + d] = run;
+                run += c;
+            }
+            st_agent(mycnt + d, run | epoch_bit(tile, wlog));
+            cnt[d] = run;
+            excl[d] = run;
+        }
+        __syncthreads();
+        total = block_excl_scan<NT>(excl, sigma, tmp);
+        for (uint32_t d = tid; d < sigma; d += NT) {
+#pragma unroll
+            for (int w = 0; w < WAVES; w++) wh[w * SMAX + d] += excl[d];
+        }
     }
     __syncthreads();
 
@@ -439,7 +474,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
         // Request the block that takes each digit's first elements (drawn by an
         // earlier tile) now; it is used after this tile's own draws are out.
         uint32_t first = kEmpty;  // pi_new entry of that block, for digit tid
-        uint32_t fsum = 0, nsum = 0;
+        uint32_t fsum = 0, nsum = 0, wsum = 0;
         for (uint32_t d = tid; d < sigma; d += NT) {
             const uint32_t bs = base[d], c = cnt[d], q0 = bs >> log2b;
             const uint32_t nfill = ((bs + c) >> log2b) - q0;
@@ -450,21 +485,33 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             tbo[d] = nwrite;
             fsum += q0;
             nsum += nfill;
+            wsum += nwrite;
         }
         for (uint32_t i = tid; i < E / 32; i += NT) fmask[i] = 0;
-        // F: draws made by earlier tiles; nfills: draws of this tile
+        // F: draws made by earlier tiles; nfills: draws of this tile; with one
+        // digit per thread, also the scan of the blocks each digit writes
         fsum = wave_sum(fsum);
         nsum = wave_sum(nsum);
+        const uint32_t wincl = SMAX <= NT ? wave_incl_scan(wsum) : 0u;
         if (lane == 0) {
             tmp[wave] = fsum;
             tmp[NT / 64 + wave] = nsum;
         }
+        if (SMAX <= NT && lane == 63) tmp[2 * (NT / 64) + wave] = wincl;
         __syncthreads();
-        uint32_t F = 0, nfills = 0;
+        uint32_t F = 0, nfills = 0, wbefore = 0, nent = 0;
 #pragma unroll
         for (int w = 0; w < NT / 64; w++) {
             F += tmp[w];
             nfills += tmp[NT / 64 + w];
+            if constexpr (SMAX <= NT) {
+                const uint32_t t = tmp[2 * (NT / 64) + w];
+                wbefore += (uint32_t)w < wave ? t : 0u;
+                nent += t;
+            }
+        }
+        if constexpr (SMAX <= NT) {
+            if (tid < sigma) tbo[tid] = wbefore + wincl - wsum;
         }
         // request the pool entries of the draws, and the done words of the
         // earlier tiles whose input blocks they are
@@ -479,8 +526,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             ohi = min<uint32_t>((uint32_t)((((uint64_t)(F + nfills) << log2b) - 1) / E) + 1, st0);
             if (olo + tid < ohi) dv = ld_agent(a.done + ((olo + tid) & wmask));
         }
-        __syncthreads();  // tmp is reused by the scan
-        const uint32_t nent = block_excl_scan<NT>(tbo, sigma, tmp);
+        if constexpr (SMAX > NT) {
+            __syncthreads();  // tmp is reused by the scan
+            nent = block_excl_scan<NT>(tbo, sigma, tmp);
+        }
         // mark the slots whose element fills a block
         for (uint32_t d = tid; d < sigma; d += NT) {
             const uint32_t nfill = nfw[d] >> 16, bs = base[d], q0 = bs >> log2b;

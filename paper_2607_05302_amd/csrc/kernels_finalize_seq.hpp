@@ -24,10 +24,7 @@ __device__ void wg_move_down(X* dst, const X* src, uint32_t count, bool overlap)
             __syncthreads();
         }
         if (i < count) dst[i] = v;
-        if (overlap) {
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-        }
+        if (overlap) wg_global_handoff();  // the next chunk may read what this one wrote
     }
 }
 
@@ -48,7 +45,7 @@ __global__ __launch_bounds__(NT) void k_finalize_seq(
     __shared__ uint32_t s_jin, s_jout, s_push, s_len, s_jfree;
     __shared__ uint64_t s_k;
     for (uint32_t L = tid; L < npi; L += NT) pinv[pi[L]] = L;
-    __syncthreads();
+    wg_global_handoff();  // thread 0 reads what every thread wrote
     uint32_t i_free = 0, j_free = 0, iP = 0, i_out = 0;
     uint64_t k = 0;
     if (tid == 0) j_free = pi[0];
@@ -79,14 +76,14 @@ __global__ __launch_bounds__(NT) void k_finalize_seq(
             if constexpr (VB != 0)
                 wg_move_down<V, NT>(blockat(Av, Tv, s_jfree, two_sigma, log2b),
                                     blockat(Av, Tv, j_out, two_sigma, log2b), b, false);
-            __syncthreads();
+            wg_global_handoff();  // the pull below may read the home block
         }
         // pull logical block i_in to A[k .. k + l)
         const bool overlap = j_in == j_out;
         wg_move_down<K, NT>(Ak + s_k, blockat(Ak, Tk, j_in, two_sigma, log2b), l, overlap);
         if constexpr (VB != 0)
             wg_move_down<V, NT>(Av + s_k, blockat(Av, Tv, j_in, two_sigma, log2b), l, overlap);
-        __syncthreads();
+        wg_global_handoff();  // later blocks are read by other threads
         if (tid == 0) {
             if (i_in < sigma + nb) {
                 if (s_push) {

@@ -116,14 +116,14 @@ __global__ __launch_bounds__(NT) void k_supertile_counts(
     }
     if (!plan) return;
     __shared__ uint32_t last;
-    __syncthreads();  // every row of this workgroup is written
-    if (tid == 0) {
-        __threadfence();  // release the rows to the other workgroups
-        last = atomicAdd(done, 1u) == gridDim.x - 1;
-        __threadfence();  // acquire the other workgroups' rows
-    }
+    // release this thread's rows at agent scope (each thread its own stores: a
+    // barrier waits for none of them), then one thread counts the workgroup in
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(done, 1u) == gridDim.x - 1;
     __syncthreads();
     if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other workgroups' rows
     const uint32_t rows = gridDim.x;
     for (uint32_t d = tid; d < sigma; d += NT) {
         uint32_t run = 0;

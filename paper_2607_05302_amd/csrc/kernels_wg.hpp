@@ -36,11 +36,10 @@
 // Wherever global memory that one thread stored is next loaded or stored by
 // another thread (the tail copy of setup and the first round; one round's
 // scatter and the next round; F1 and F2; one array and the next in the same T),
-// every thread first waits for its own stores to complete, then the workgroup
-// meets at a barrier, then the compute unit's cached lines are dropped
-// (wg_global_handoff).  A barrier alone waits for neither stores nor loads, so
-// where a thread loads what another thread overwrites after a barrier (F2's
-// batches), the loads are waited for before it.
+// the workgroup passes a full hand-off (wg_global_handoff: release at agent
+// scope, barrier, acquire at agent scope).  A barrier alone waits for neither
+// stores nor loads, so where a thread loads what another thread overwrites after
+// a barrier (F2's batches), the loads are waited for before it.
 #pragma once
 
 #include "common.hpp"
@@ -69,17 +68,6 @@ inline uint64_t wg_slot_bytes(int kb, int vb)
 {
     const uint64_t t = 2ull * kWgSigma << kWgLog2b;
     return (t * (kb + vb) + 255) / 256 * 256;
-}
-
-// Hand-off of global memory between the threads of the workgroup: every store of
-// this thread has completed, every thread is past the barrier, and lines this
-// compute unit cached before are dropped, so the loads after it see the stores
-// before it, whichever thread made them.
-__device__ __forceinline__ void wg_global_handoff()
-{
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 template <int KB, int VB>
@@ -148,11 +136,22 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
         // ---- digit histograms of every key position (one pass) -------------------
         for (uint32_t i = tid; i < nt * sigma; i += NT) (&hist[0][0])[i] = 0;
         __syncthreads();
-        for (uint32_t i = tid; i < n; i += NT) {
-            const K x = A[i];
+        for (uint32_t i0 = 0; i0 < n; i0 += 4 * NT) {
+            K x[4];
 #pragma unroll
-            for (uint32_t t = 0; t < nt; t++)
-                atomicAdd(&hist[t][(uint32_t)(x >> (kWgBits * (nt - 1 - t))) & dmask], 1u);
+            for (uint32_t u = 0; u < 4; u++) {  // four loads in flight per thread
+                const uint32_t i = i0 + u * NT + tid;
+                x[u] = i < n ? A[i] : (K)0;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; u++) {
+                if (i0 + u * NT + tid < n) {
+#pragma unroll
+                    for (uint32_t t = 0; t < nt; t++)
+                        atomicAdd(&hist[t][(uint32_t)(x[u] >> (kWgBits * (nt - 1 - t))) & dmask],
+                                  1u);
+                }
+            }
         }
         // ---- setup (Alg. 4) ----------------------------------------------------------
         const uint32_t f0 = sigma + nb + 1;
@@ -528,8 +527,7 @@ __global__ __launch_bounds__(1024) void k_wg_list(const uint64_t* __restrict__ o
     const uint32_t tid = threadIdx.x;
     if (tid < 64) cls[tid] = 0;
     for (uint32_t i = tid; i < count; i += 1024) list[i] = 0xFFFFFFFFu;
-    __builtin_amdgcn_s_waitcnt(0);  // the marks land before the entries below
-    __syncthreads();
+    wg_global_handoff();  // the marks land before the entries below
     for (uint32_t i = tid; i < nseg; i += 1024) {
         const uint64_t n = offsets[i + 1] - offsets[i];
         if (n > lo && n <= hi) atomicAdd(&cls[__clzll(n)], 1u);
