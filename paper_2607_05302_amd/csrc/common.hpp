@@ -116,17 +116,18 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 
 // Hand-off of global memory between the threads of one workgroup: every store a
 // thread made before it is visible to every load any thread of the workgroup
-// makes after it.  Release at agent scope (the stores written back to L2 and
-// complete), a barrier, then acquire at agent scope (cached lines dropped).
-// Waiting for the stores (s_waitcnt) and dropping the compute unit's lines
-// around a barrier was not enough on gfx950: with that weaker form, a
-// one-workgroup sort read stale data now and then.  Contains a barrier.
+// makes after it.  Each thread releases at agent scope (its stores complete and
+// written back from L2), the workgroup meets at a barrier, and each thread
+// acquires at agent scope (cached lines dropped).  Waiting for the stores
+// (s_waitcnt) and dropping the compute unit's lines around a barrier, without
+// the release, was not enough on gfx950: a one-workgroup sort with that weaker
+// form read stale data now and then.  Contains a barrier.
 __device__ __forceinline__ void wg_global_handoff()
 {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Exclusive prefix sum, in place, of a[0..count) in LDS, by all NT threads of the
