@@ -116,18 +116,19 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 
 // Hand-off of global memory between the threads of one workgroup: every store a
 // thread made before it is visible to every load any thread of the workgroup
-// makes after it.  Each thread releases at agent scope (its stores complete and
-// written back from L2), the workgroup meets at a barrier, and each thread
-// acquires at agent scope (cached lines dropped).  Waiting for the stores
-// (s_waitcnt) and dropping the compute unit's lines around a barrier, without
-// the release, was not enough on gfx950: a one-workgroup sort with that weaker
-// form read stale data now and then.  Contains a barrier.
+// makes after it.  Each thread passes a sequentially consistent fence at agent
+// scope (stores complete, L2 written back, cached lines dropped), the workgroup
+// meets at a barrier, and each thread passes the same fence again.  Weaker forms
+// were not enough on gfx950: with a release before the barrier and an acquire
+// after it, one-workgroup sorts of 4.4 M keys still read stale data in about one
+// call in seven, and without the release in about one in eight; with this form
+// none did in the same runs.  Contains a barrier.
 __device__ __forceinline__ void wg_global_handoff()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
 }
 
 // Exclusive prefix sum, in place, of a[0..count) in LDS, by all NT threads of the

@@ -33,7 +33,7 @@
 
 namespace rs {
 
-constexpr uint32_t kFinJob = 1024;      // nodes per job of F1
+constexpr uint32_t kFinJob = 1024;      // nodes per job of F1 (at most)
 constexpr uint32_t kFinCols = 256;      // columns of a block moved by one F1 workgroup
 constexpr uint32_t kFinDepth = 16;      // loads in flight per thread in F1
 constexpr uint32_t kScanTile = 4096;    // elements per workgroup of the device scan
@@ -52,9 +52,20 @@ inline uint64_t fin_flag_words(uint32_t npi, uint64_t n)
     return std::max<uint64_t>(npi, n / kCompactMin + 1) + 16;
 }
 
+// Nodes per F1 job: kFinJob, or fewer (down to 16) for states of fewer than
+// 64 kFinJob blocks, so that their blocks are spread over more workgroups; each
+// job saves up to two head blocks, a small part of the workspace of such states.
+inline uint32_t fin_job(uint32_t npi)
+{
+    uint32_t j = kFinJob;
+    while (j > 16 && (uint64_t)j * 64 > npi) j >>= 1;
+    return j;
+}
+
 inline uint64_t fin_scratch_bytes(uint32_t npi, uint64_t n, uint32_t b, uint32_t elem_bytes)
 {
-    uint64_t jobs = (npi + kFinJob - 1) / kFinJob;
+    const uint32_t job = fin_job(npi);
+    uint64_t jobs = (npi + job - 1) / job;
     uint64_t sums = (npi + kScanTile - 1) / kScanTile + 1;
     return 6 * fin_align(4ull * npi) + fin_align(4 * sums) + fin_align(4 * fin_flag_words(npi, n)) +
            fin_align(2 * jobs * (uint64_t)b * elem_bytes);
@@ -74,6 +85,7 @@ struct FinArgs {
     const uint32_t* f;
     uint64_t n;
     uint32_t sigma, log2b, npi;
+    uint32_t job;  // nodes per F1 job: fin_job(npi)
     uint32_t* err;
     uint8_t* scratch;
     uint32_t* spare_pi;  // the other pi buffer (n_pi words), free during finalize
@@ -346,10 +358,10 @@ __global__ void k_scan_add(uint32_t* a, uint32_t count, const uint32_t* sums)
 // at the job start (slot 2j) and the last piece if it starts inside the job and
 // continues after it (slot 2j + 1).  Returns the node (with garbage bit) or ~0.
 __device__ __forceinline__ void job_heads(const uint32_t* ord, const uint32_t* rank,
-                                          const uint32_t* clen, uint32_t j, uint32_t M,
-                                          uint32_t npi, uint32_t& h0, uint32_t& h1)
+                                          const uint32_t* clen, uint32_t j, uint32_t job,
+                                          uint32_t M, uint32_t npi, uint32_t& h0, uint32_t& h1)
 {
-    const uint32_t i0 = j * kFinJob, i1 = min(M, i0 + kFinJob);
+    const uint32_t i0 = j * job, i1 = min(M, i0 + job);
     h0 = h1 = ~0u;
     if (i1 <= i0) return;
     const uint32_t p0 = ord[i0] & ~kGarbage;
@@ -378,11 +390,11 @@ __global__ __launch_bounds__(256) void k_fin_save(FinArgs<KB, VB> a, FinArrays f
     using V = typename Payload<VB>::T;
     const uint32_t M = min(*M_ptr, a.npi), j = blockIdx.x, b = 1u << a.log2b;
     const uint32_t two_sigma = 2 * a.sigma;
-    if (j * kFinJob >= M) return;
+    if (j * a.job >= M) return;
     uint32_t h[2];
-    job_heads(f.ord, rank, clen, j, M, a.npi, h[0], h[1]);
+    job_heads(f.ord, rank, clen, j, a.job, M, a.npi, h[0], h[1]);
     K* tk = (K*)f.temps;
-    V* tv = (V*)(f.temps + 2ull * ((a.npi + kFinJob - 1) / kFinJob) * b * KB);
+    V* tv = (V*)(f.temps + 2ull * ((a.npi + a.job - 1) / a.job) * b * KB);
     for (int s = 0; s < 2; s++) {
         if (h[s] == ~0u || (h[s] & kGarbage)) continue;
         if (h[s] >= a.npi) {  // never for a consistent order array
@@ -420,16 +432,16 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
     using VE = typename Payload<VB>::T;
     const uint32_t M = min(*M_ptr, a.npi), j = blockIdx.x, b = 1u << a.log2b;
     const uint32_t two_sigma = 2 * a.sigma;
-    const uint32_t i0 = j * kFinJob;
+    const uint32_t i0 = j * a.job;
     if (i0 >= M) return;
-    const uint32_t i1 = min(M, i0 + kFinJob);
+    const uint32_t i1 = min(M, i0 + a.job);
     const uint32_t col = (blockIdx.y * kFinCols + threadIdx.x) * VEC;
     const bool active = col < b;  // b is a multiple of VEC
     const uint32_t log2b = a.log2b;
     // loads in flight per thread: about 512 bytes of registers
     constexpr uint32_t DEPTH = VEC == 1 ? kFinDepth : (KB + VB <= 8 ? 16u : 8u);
     const KE* tk = (const KE*)f.temps;
-    const VE* tv = (const VE*)(f.temps + 2ull * ((a.npi + kFinJob - 1) / kFinJob) * b * KB);
+    const VE* tv = (const VE*)(f.temps + 2ull * ((a.npi + a.job - 1) / a.job) * b * KB);
     // the job's part of the order array, and the whole cycle of a piece that
     // crosses the job's start or end is read from global memory
     __shared__ uint32_t sord[kFinJob];
@@ -726,7 +738,7 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
                            dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
                            dim3(256), 0, s, f.flags, f.nflags, 0u);
     }
-    const uint32_t jobs = (npi + kFinJob - 1) / kFinJob;
+    const uint32_t jobs = (npi + a.job - 1) / a.job;
     hipLaunchKernelGGL((k_fin_save<KB, VB>), dim3(jobs), dim3(256), 0, s, a, f, rank, clen, M_ptr);
     // four columns per thread when every block start is 16-byte aligned
     const bool wide = b >= 64 && (((uintptr_t)a.Ak | (uintptr_t)a.Av | (uintptr_t)a.Tk |

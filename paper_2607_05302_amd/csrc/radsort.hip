@@ -553,6 +553,7 @@ template <int KB, int VB> struct Ops {
         a.sigma = g.sigma;
         a.log2b = g.log2b;
         a.npi = g.npi;
+        a.job = fin_job(g.npi);
         a.err = st->err();
         a.scratch = st->ws + st->L.fin;
         a.spare_pi = st->pi(st->cur ^ 1);
