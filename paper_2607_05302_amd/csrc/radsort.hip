@@ -39,7 +39,7 @@ radsort_stats g_stats{};
     } while (0)
 
 constexpr uint32_t kRingWords = 1u << 19;  // look-back ring: 2^ring_log2 * sigma count words
-constexpr uint32_t kSuperLog2 = 4;         // tiles per super-tile: 16, or enough to hold a block
+constexpr uint32_t kSuperLog2 = 3;         // tiles per super-tile: 8, or enough to hold a block
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
