@@ -387,7 +387,7 @@ def bench_serving(args):
         srv.run(trace[: min(8, len(trace))])  # warm-up: kernels loaded, streams made
         torch.cuda.empty_cache()
         log(f"bench: serving {len(trace)} requests with {method}")
-        out = srv.run(trace)
+        out = srv.run(trace, verify=True)
         res[method] = serve.summarize(trace, out)
         log(f"bench: {method}: {res[method]}")
         del srv
@@ -404,6 +404,7 @@ def bench_serving(args):
                                f"{args.slots} slots", "offered_rps": serve.offered_load(trace)},
         "radsort": r, "oop": res["oop"],
         "p99_ratio_oop_over_radsort": res["oop"]["p99_ms"] / r["p99_ms"],
+        "verified": r["wrong_results"] == 0 and res["oop"]["wrong_results"] == 0,
     }
     print(json.dumps(out), flush=True)
 

@@ -87,10 +87,28 @@ class Server:
             done.record(stream)
         return keys, vals, ws, done
 
-    def run(self, trace, keep=()):
+    def _check(self, req: Request, keys, vals) -> bool:
+        """On the device, after the request's sort: keys ascending (unsigned), the
+        same multiset sums as the input keys drawn again from the request's seed,
+        and the index payload summing to n (n - 1) / 2.  A check, not a proof: it
+        catches lost, duplicated and misplaced records."""
+        import torch
+        import workloads
+        if req.key_bytes == 4:
+            k = keys.to(torch.int64) & 0xFFFFFFFF
+        else:
+            k = keys ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=keys.device)
+        ok = req.n < 2 or bool((k[1:] >= k[:-1]).all())
+        k0 = workloads.uniform_t(req.seed, req.n, req.key_bytes, self.device)
+        ok = ok and bool((k0.to(torch.int64).sum() == keys.to(torch.int64).sum()).item())
+        return ok and int(vals.to(torch.int64).sum().item()) == req.n * (req.n - 1) // 2
+
+    def run(self, trace, keep=(), verify=False):
         """Serves the trace in real time.  Returns per-request latencies (ms, from
-        arrival to the end of its sort on the GPU), the makespan, and the sorted
-        arrays of the requests whose ids are in ``keep`` (on the host)."""
+        arrival to the end of its sort on the GPU), the makespan, the sorted arrays
+        of the requests whose ids are in ``keep`` (on the host), and with verify the
+        ids of the requests whose result failed `_check` (checked when each
+        request completes, on its stream, which adds device work to the run)."""
         import torch
         keep = set(keep)
         pending = collections.deque(sorted(trace, key=lambda r: r.arrival))
@@ -98,7 +116,7 @@ class Server:
         free = list(range(len(self.streams)))
         active = {}
         used, peak_used, peak_active = 0, 0, 0
-        out = {"latency_ms": {}, "kept": {}, "admit_wait_ms": {}}
+        out = {"latency_ms": {}, "kept": {}, "admit_wait_ms": {}, "bad": []}
         torch.cuda.synchronize(self.device)
         t0_ev = torch.cuda.Event(enable_timing=True)
         t0_ev.record(torch.cuda.current_stream(self.device))
@@ -116,6 +134,10 @@ class Server:
                     out["latency_ms"][req.rid] = t0_ev.elapsed_time(done) - req.arrival * 1e3
                     if req.rid in keep:
                         out["kept"][req.rid] = (keys.cpu().numpy(), vals.cpu().numpy())
+                    if verify:
+                        with torch.cuda.stream(self.streams[slot]):
+                            if not self._check(req, keys, vals):
+                                out["bad"].append(req.rid)
                     del active[slot]
                     free.append(slot)
                     used -= fp
@@ -159,6 +181,7 @@ def summarize(trace, out) -> dict:
         "peak_footprint_bytes": int(out["peak_footprint_bytes"]),
         "peak_active": int(out["peak_active"]),
         "mean_admit_wait_ms": float(np.mean(list(out["admit_wait_ms"].values()))),
+        "wrong_results": len(out.get("bad", [])),
     }
 
 
