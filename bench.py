@@ -404,7 +404,8 @@ def bench_serving(args):
                                f"{args.slots} slots", "offered_rps": serve.offered_load(trace)},
         "radsort": r, "oop": res["oop"],
         "p99_ratio_oop_over_radsort": res["oop"]["p99_ms"] / r["p99_ms"],
-        "verified": r["wrong_results"] == 0 and res["oop"]["wrong_results"] == 0,
+        "verified": all(x["wrong_results"] == 0 and x["device_errors"] == 0
+                        for x in (r, res["oop"])),
     }
     print(json.dumps(out), flush=True)
 

@@ -108,6 +108,22 @@ int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
                        int payload_bytes, int digit_bits, const radsort_opts* opts,
                        void* stream);
 
+/*
+ * radsort_workspace_error -- the device-side error word that the last
+ * radsort_sort_pairs (out_of_place = 0) or radsort_oop_sort_pairs (out_of_place = 1)
+ * call with this workspace left, for callers that pass their own workspace and no
+ * RADSORT_F_CHECK, so that the sort itself returned without waiting.  n, key_bytes,
+ * payload_bytes, digit_bits and opts (workspace, workspace_bytes, block_elems) must
+ * be those of that call.  Enqueues a 4-byte copy on `stream` and waits for the
+ * stream.  *error_bits (may be NULL) receives the word: 0, or bit 0 when a bounded
+ * wait between workgroups gave up, bit 1 when an index fell outside its array (the
+ * data are then unspecified).  Returns RADSORT_OK for 0, RADSORT_E_TIMEOUT for any
+ * bit, RADSORT_E_INVALID / RADSORT_E_NOMEM for a missing or short workspace.
+ */
+int radsort_workspace_error(const void* workspace, uint64_t n, int key_bytes,
+                            int payload_bytes, int digit_bits, const radsort_opts* opts,
+                            int out_of_place, uint32_t* error_bits, void* stream);
+
 /* radsort_sort -- radsort_sort_pairs without payload and with default options. */
 int radsort_sort(void* keys, uint64_t n, int key_bytes, int digit_bits, void* stream);
 

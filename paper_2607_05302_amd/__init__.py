@@ -33,7 +33,7 @@ ABI = [
     "radsort_state_logical", "radsort_state_dims", "radsort_state_destroy",
     "radsort_sort_segments", "radsort_segments_workspace_bytes",
     "radsort_state_blocks", "radsort_state_planes", "radsort_state_count",
-    "radsort_state_truncate", "radsort_state_restart",
+    "radsort_state_truncate", "radsort_state_restart", "radsort_workspace_error",
 ]
 SEG_CLASSES = 32
 
@@ -85,6 +85,7 @@ def load(path: str | None = None):
         "radsort_workspace_bytes": (u64, [u64, i32, i32, i32, op]),
         "radsort_oop_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
         "radsort_oop_workspace_bytes": (u64, [u64, i32, i32, i32, op]),
+        "radsort_workspace_error": (i32, [vp, u64, i32, i32, i32, op, i32, u32p, vp]),
         "radsort_histograms": (i32, [vp, u64, i32, i32, vp, vp]),
         "radsort_last_stats": (i32, [ctypes.POINTER(Stats)]),
         "radsort_strerror": (ctypes.c_char_p, [i32]),
@@ -204,6 +205,27 @@ def oop_sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, w
             keys.numel(), kb, vb, digit_bits, ctypes.byref(o), _stream(stream, keys.device))
     _check(rc)
     return keys, payload
+
+
+def workspace_error(keys, payload=None, digit_bits=8, block_elems=1024, stream=None,
+                    workspace=None, out_of_place=False) -> int:
+    """The error bits that the last sort_ (or oop_sort_ with out_of_place) of these
+    arrays with this workspace left (radsort_workspace_error): 0, or bit 0 when a
+    bounded wait between workgroups gave up, bit 1 for an index out of range.
+    Waits for the stream."""
+    kb, vb = _validate(keys, payload)
+    if workspace is None:
+        raise ValueError("workspace_error needs the workspace the sort used")
+    o = _opts(block_elems, workspace, 0)
+    bits = ctypes.c_uint32(0)
+    with _device(keys):
+        rc = load().radsort_workspace_error(
+            ctypes.c_void_p(workspace.data_ptr()), keys.numel(), kb, vb, digit_bits,
+            ctypes.byref(o), 1 if out_of_place else 0, ctypes.byref(bits),
+            _stream(stream, keys.device))
+    if rc not in (0, E_TIMEOUT):
+        _check(rc)
+    return int(bits.value)
 
 
 def seg_tuning(table):

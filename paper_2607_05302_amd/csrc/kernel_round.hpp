@@ -539,6 +539,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
                 atomicOr(&fmask[s >> 5], 1u << (s & 31));
             }
         }
+        // The drawn blocks are input blocks sigma + F .. sigma + F + nfills - 1.  Those
+        // of this super-tile were loaded before their tiles' counts, which the
+        // look-back read; for earlier tiles wait until they are done.  The wait ends
+        // before the draws are published (after the barrier below): later tiles
+        // that continue a drawn block write into it as soon as they see its entry
+        // in pi_new, and they make no wait of their own for its old contents.
+        for (uint32_t o = olo + tid; o < ohi; o += NT) {
+            const uint32_t* w = a.done + (o & wmask);
+            uint32_t v = o == olo + tid ? dv : ld_agent(w), spins = 0;
+            while (v <= o) {
+                if (spin_give_up(++spins, a.err)) break;
+                spin_pause();
+                v = ld_agent(w);
+            }
+        }
         __syncthreads();
         for (uint32_t i = tid; i < E / 32; i += NT) fpref[i] = __popc(fmask[i]);
         if (tid < nfills) pool[tid] = pv;
@@ -566,18 +581,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
                     phys = 0;
                 }
                 if (i < nwrite) tphys[t0 + i] = phys;
-            }
-        }
-        // The drawn blocks are input blocks sigma + F .. sigma + F + nfills - 1.  Those
-        // of this super-tile were loaded before their tiles' counts, which the
-        // look-back read; for earlier tiles wait until they are done.
-        for (uint32_t o = olo + tid; o < ohi; o += NT) {
-            const uint32_t* w = a.done + (o & wmask);
-            uint32_t v = o == olo + tid ? dv : ld_agent(w), spins = 0;
-            while (v <= o) {
-                if (spin_give_up(++spins, a.err)) break;
-                spin_pause();
-                v = ld_agent(w);
             }
         }
         // the block of each digit's first elements

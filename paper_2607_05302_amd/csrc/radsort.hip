@@ -1087,6 +1087,27 @@ uint64_t radsort_oop_workspace_bytes(uint64_t n, int key_bytes, int payload_byte
     return make_layout(g, true).total;
 }
 
+int radsort_workspace_error(const void* workspace, uint64_t n, int key_bytes, int payload_bytes,
+                            int digit_bits, const radsort_opts* opts, int out_of_place,
+                            uint32_t* error_bits, void* stream)
+{
+    if (error_bits) *error_bits = 0;
+    if (!workspace || !opts) return RADSORT_E_INVALID;
+    Geo g;
+    int rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts);
+    if (rc) return rc;
+    if (n <= 1) return RADSORT_OK;  // such a call runs nothing
+    const Layout L = make_layout(g, out_of_place != 0);
+    if (opts->workspace_bytes < L.total) return RADSORT_E_NOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t e = 0;
+    RS_HIP(hipMemcpyAsync(&e, (const uint8_t*)workspace + L.ctr + 4ull * g.nt, 4,
+                          hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    if (error_bits) *error_bits = e;
+    return e ? RADSORT_E_TIMEOUT : RADSORT_OK;
+}
+
 int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes, int payload_bytes,
                        int digit_bits, const radsort_opts* opts, void* stream)
 {

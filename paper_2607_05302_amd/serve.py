@@ -110,13 +110,15 @@ class Server:
         ids of the requests whose result failed `_check` (checked when each
         request completes, on its stream, which adds device work to the run)."""
         import torch
+
+        import paper_2607_05302_amd as radsort
         keep = set(keep)
         pending = collections.deque(sorted(trace, key=lambda r: r.arrival))
         queue = collections.deque()
         free = list(range(len(self.streams)))
         active = {}
         used, peak_used, peak_active = 0, 0, 0
-        out = {"latency_ms": {}, "kept": {}, "admit_wait_ms": {}, "bad": []}
+        out = {"latency_ms": {}, "kept": {}, "admit_wait_ms": {}, "bad": [], "device_errors": []}
         torch.cuda.synchronize(self.device)
         t0_ev = torch.cuda.Event(enable_timing=True)
         t0_ev.record(torch.cuda.current_stream(self.device))
@@ -138,6 +140,10 @@ class Server:
                         with torch.cuda.stream(self.streams[slot]):
                             if not self._check(req, keys, vals):
                                 out["bad"].append(req.rid)
+                        if radsort.workspace_error(keys, vals, block_elems=self.block,
+                                                   stream=self.streams[slot], workspace=ws,
+                                                   out_of_place=self.method == "oop"):
+                            out["device_errors"].append(req.rid)
                     del active[slot]
                     free.append(slot)
                     used -= fp
@@ -182,6 +188,7 @@ def summarize(trace, out) -> dict:
         "peak_active": int(out["peak_active"]),
         "mean_admit_wait_ms": float(np.mean(list(out["admit_wait_ms"].values()))),
         "wrong_results": len(out.get("bad", [])),
+        "device_errors": len(out.get("device_errors", [])),
     }
 
 

@@ -101,6 +101,25 @@ def test_null_pointers_rejected():
     assert lib.radsort_histograms(fake, 10, 4, 8, None, None) == radsort.E_INVALID
 
 
+def test_workspace_error_argument_checks():
+    lib = radsort.load()
+    fake = ctypes.c_void_p(0x1000)
+    bits = ctypes.c_uint32(7)
+    assert lib.radsort_workspace_error(None, 1000, 4, 4, 8, None, 0, ctypes.byref(bits),
+                                       None) == radsort.E_INVALID
+    assert bits.value == 0
+    o = radsort.Opts()
+    o.block_elems, o.workspace, o.workspace_bytes = 1024, fake, 16
+    for oop in (0, 1):
+        assert lib.radsort_workspace_error(fake, 100000, 4, 4, 8, ctypes.byref(o), oop, None,
+                                           None) == radsort.E_NOMEM
+    o.workspace_bytes = 1 << 40
+    assert lib.radsort_workspace_error(fake, 1, 4, 4, 8, ctypes.byref(o), 0, None,
+                                       None) == radsort.OK
+    assert lib.radsort_workspace_error(fake, 1000, 3, 4, 8, ctypes.byref(o), 0, None,
+                                       None) == radsort.E_INVALID
+
+
 def test_trivial_sizes_are_no_ops():
     lib = radsort.load()
     # n <= 1 returns before anything is enqueued, so no device is needed
