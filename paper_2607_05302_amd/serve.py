@@ -12,6 +12,14 @@ Radsort admits about twice as much work.
 The sorts run with RADSORT_F_SHARED: their kernels need no co-resident grid, so
 several can share the GPU.  Inputs are drawn on the device when a request is
 admitted (the seeded streams of `workloads`), on the request's stream.
+
+Device memory: one buffer of the budget's size, allocated when the server starts,
+carved first-fit into one region per admitted request (keys, payload, workspace)
+by `Arena`.  A request is admitted when a free range holds its region, so the
+budget is a hard limit, and the loop makes no device allocation of that size
+while it runs (allocating and freeing arrays of ever different sizes through
+torch's caching allocator grew its reserve to the whole device, and the frees that
+followed stalled every stream for up to seconds).
 """
 from __future__ import annotations
 
@@ -46,12 +54,69 @@ def make_trace(seed: int, count: int, rate: float, lo_log2: float = 12, hi_log2:
                     seed * 1000003 + i) for i in range(count)]
 
 
-def footprint(req: Request, method: str, block: int = 1024) -> int:
+ALIGN = 256  # bytes; every array of a region starts on this boundary
+
+
+def _align(x: int) -> int:
+    return (x + ALIGN - 1) // ALIGN * ALIGN
+
+
+def region(req: Request, method: str, block: int = 1024):
+    """Byte offsets of the keys, the payload and the workspace within a request's
+    region, and the region's size."""
     import paper_2607_05302_amd as radsort
-    data = req.n * (req.key_bytes + 4)
-    if method == "radsort":
-        return data + radsort.workspace_bytes(req.n, req.key_bytes, 4, 8, block)
-    return data + radsort.oop_workspace_bytes(req.n, req.key_bytes, 4, 8, block)
+    wsb = (radsort.workspace_bytes if method == "radsort" else radsort.oop_workspace_bytes)(
+        req.n, req.key_bytes, 4, 8, block)
+    o_v = _align(req.n * req.key_bytes)
+    o_w = o_v + _align(req.n * 4)
+    return 0, o_v, o_w, o_w + _align(wsb)
+
+
+def footprint(req: Request, method: str, block: int = 1024) -> int:
+    """Device bytes a request holds while it runs: keys and payload plus Radsort's
+    workspace, or plus the baseline's second arrays (each array 256-byte aligned)."""
+    return region(req, method, block)[3]
+
+
+class Arena:
+    """First-fit allocation of byte ranges in [0, size): `alloc` returns the lowest
+    offset of a free range that holds ``nbytes`` (rounded up to ALIGN), or None;
+    `release` returns a range and merges it with free neighbours."""
+
+    def __init__(self, size: int):
+        self.size = size // ALIGN * ALIGN
+        self.free = [(0, self.size)] if self.size else []  # (offset, length), by offset
+
+    def alloc(self, nbytes: int):
+        need = _align(max(nbytes, 1))
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= need:
+                if ln == need:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + need, ln - need)
+                return off
+        return None
+
+    def release(self, off: int, nbytes: int):
+        ln = _align(max(nbytes, 1))
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] > off:
+            raise ValueError("range released twice or overlaps a free range")
+        if i < len(self.free) and off + ln > self.free[i][0]:
+            raise ValueError("range released twice or overlaps a free range")
+        self.free.insert(i, (off, ln))
+        if i + 1 < len(self.free) and off + ln == self.free[i + 1][0]:
+            self.free[i] = (off, ln + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    def free_bytes(self) -> int:
+        return sum(ln for _, ln in self.free)
 
 
 class Server:
@@ -63,26 +128,30 @@ class Server:
         self.method, self.budget, self.block = method, float(budget), block
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        self.arena = Arena(int(budget))
+        self.buf = torch.empty(self.arena.size, dtype=torch.uint8, device=self.device)
 
-    def _start(self, req: Request, stream):
+    def _start(self, req: Request, stream, base: int):
+        """Draws the request's input into its region at byte offset ``base`` of the
+        arena and sorts it, all on ``stream``."""
         import torch
 
         import paper_2607_05302_amd as radsort
         import workloads
+        o_k, o_v, o_w, end = region(req, self.method, self.block)
+        kdt = torch.int32 if req.key_bytes == 4 else torch.int64
+        keys = self.buf[base + o_k: base + o_k + req.n * req.key_bytes].view(kdt)
+        vals = self.buf[base + o_v: base + o_v + req.n * 4].view(torch.int32)
+        ws = self.buf[base + o_w: base + end]
         with torch.cuda.stream(stream):
-            keys = workloads.uniform_t(req.seed, req.n, req.key_bytes, self.device)
-            vals = torch.arange(req.n, dtype=torch.int32, device=self.device)
-            if self.method == "radsort":
-                ws = torch.empty(radsort.workspace_bytes(req.n, req.key_bytes, 4, 8, self.block),
-                                 dtype=torch.uint8, device=self.device)
-                radsort.sort_(keys, vals, block_elems=self.block, stream=stream, workspace=ws,
-                              shared=True)
-            else:
-                ws = torch.empty(radsort.oop_workspace_bytes(req.n, req.key_bytes, 4, 8,
-                                                             self.block),
-                                 dtype=torch.uint8, device=self.device)
-                radsort.oop_sort_(keys, vals, block_elems=self.block, stream=stream,
-                                  workspace=ws, shared=True)
+            chunk = 1 << 24  # bounded temporaries: the input is drawn in pieces
+            for lo in range(0, req.n, chunk):
+                hi = min(req.n, lo + chunk)
+                keys[lo:hi] = workloads.uniform_t(req.seed, hi - lo, req.key_bytes, self.device,
+                                                  start=lo)
+                torch.arange(lo, hi, dtype=torch.int32, device=self.device, out=vals[lo:hi])
+            sort = radsort.sort_ if self.method == "radsort" else radsort.oop_sort_
+            sort(keys, vals, block_elems=self.block, stream=stream, workspace=ws, shared=True)
             done = torch.cuda.Event(enable_timing=True)
             done.record(stream)
         return keys, vals, ws, done
@@ -94,14 +163,21 @@ class Server:
         catches lost, duplicated and misplaced records."""
         import torch
         import workloads
-        if req.key_bytes == 4:
-            k = keys.to(torch.int64) & 0xFFFFFFFF
-        else:
-            k = keys ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=keys.device)
-        ok = req.n < 2 or bool((k[1:] >= k[:-1]).all())
-        k0 = workloads.uniform_t(req.seed, req.n, req.key_bytes, self.device)
-        ok = ok and bool((k0.to(torch.int64).sum() == keys.to(torch.int64).sum()).item())
-        return ok and int(vals.to(torch.int64).sum().item()) == req.n * (req.n - 1) // 2
+        flip = torch.tensor(-(1 << 63), dtype=torch.int64, device=keys.device)
+        unsorted = torch.zeros((), dtype=torch.int64, device=keys.device)
+        ksum = torch.zeros((), dtype=torch.int64, device=keys.device)
+        vsum = torch.zeros((), dtype=torch.int64, device=keys.device)
+        chunk = 1 << 24  # bounded temporaries; neighbouring chunks overlap by one key
+        for lo in range(0, req.n, chunk):
+            hi = min(req.n, lo + chunk)
+            k = keys[max(lo - 1, 0):hi]
+            k = (k.to(torch.int64) & 0xFFFFFFFF) if req.key_bytes == 4 else k ^ flip
+            unsorted += (k[1:] < k[:-1]).sum()
+            k0 = workloads.uniform_t(req.seed, hi - lo, req.key_bytes, self.device, start=lo)
+            ksum += k0.to(torch.int64).sum() - keys[lo:hi].to(torch.int64).sum()
+            vsum += vals[lo:hi].to(torch.int64).sum()
+        return (int(unsorted.item()) == 0 and int(ksum.item()) == 0
+                and int(vsum.item()) == req.n * (req.n - 1) // 2)
 
     def run(self, trace, keep=(), verify=False):
         """Serves the trace in real time.  Returns per-request latencies (ms, from
@@ -131,7 +207,7 @@ class Server:
                 queue.append(pending.popleft())
                 progressed = True
             for slot in list(active):
-                req, keys, vals, ws, done, fp = active[slot]
+                req, keys, vals, ws, done, fp, base = active[slot]
                 if done.query():
                     out["latency_ms"][req.rid] = t0_ev.elapsed_time(done) - req.arrival * 1e3
                     if req.rid in keep:
@@ -144,21 +220,23 @@ class Server:
                                                    stream=self.streams[slot], workspace=ws,
                                                    out_of_place=self.method == "oop"):
                             out["device_errors"].append(req.rid)
-                    del active[slot]
+                    del active[slot], keys, vals, ws
+                    self.arena.release(base, fp)
                     free.append(slot)
                     used -= fp
                     progressed = True
             while queue and free:
                 fp = footprint(queue[0], self.method, self.block)
-                if fp > self.budget:
+                if fp > self.arena.size:
                     raise ValueError(f"request {queue[0].rid} needs {fp} bytes, more than the budget")
-                if used + fp > self.budget:
+                base = self.arena.alloc(fp)
+                if base is None:
                     break  # first come, first served: wait for memory
                 req = queue.popleft()
                 slot = free.pop()
                 out["admit_wait_ms"][req.rid] = (time.perf_counter() - t0 - req.arrival) * 1e3
-                keys, vals, ws, done = self._start(req, self.streams[slot])
-                active[slot] = (req, keys, vals, ws, done, fp)
+                keys, vals, ws, done = self._start(req, self.streams[slot], base)
+                active[slot] = (req, keys, vals, ws, done, fp, base)
                 used += fp
                 peak_used = max(peak_used, used)
                 peak_active = max(peak_active, len(active))

@@ -186,3 +186,18 @@ def test_segments_one_workgroup_path_repeated():
             a, b = int(offsets[i]), int(offsets[i + 1])
             assert np.array_equal(got_k[a:b].astype(np.uint64), k), (rep, sizes[i])
             assert np.array_equal(got_v[a:b], v), (rep, sizes[i])
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_segments_lanes_run_concurrently(kb):
+    """Eight arrays past the one-workgroup path: the lanes sort them on four
+    streams at once in the dynamic launch form (the form whose tiles can run far
+    apart in time), each array against the oracle."""
+    sizes = [WG_MAX + 1 + i * 1_300_021 for i in range(8)]
+    say(f"segments lanes kb={kb} total={sum(sizes)}")
+    offsets, keys, vals = batch(0x5EA + kb, sizes, kb)
+    dk, dv = to_dev(keys), to_dev(vals)
+    radsort.sort_segments_(dk, dv, offsets, check=True)
+    ek, ev = expected(offsets, keys, vals, kb)
+    assert np.array_equal(dk.cpu().numpy().view(NP[kb]).astype(np.uint64), ek)
+    assert np.array_equal(dv.cpu().numpy().view(np.uint32).astype(np.uint64), ev)

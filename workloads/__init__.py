@@ -169,8 +169,9 @@ def _high32_t(w):
     return torch.where(h >= 1 << 31, h - (1 << 32), h).to(torch.int32)
 
 
-def uniform_t(seed: int, n: int, key_bytes: int, device):
-    w = words_t(seed, n, device)
+def uniform_t(seed: int, n: int, key_bytes: int, device, start: int = 0):
+    """Keys start .. start + n - 1 of ``uniform(seed, ...)`` on ``device``."""
+    w = words_t(seed, n, device, start=start)
     return _high32_t(w) if key_bytes == 4 else w
 
 
