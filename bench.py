@@ -395,7 +395,8 @@ def bench_serving(args):
     r = res["radsort"]
     out = {
         "metric": "sort serving: keys/s and p50/p99 latency, Poisson arrivals, sizes log-uniform "
-                  "in [2^12, 2^28], 50/50 uint32/uint64 keys, 64 GB budget, Radsort vs out-of-place",
+                  f"in [2^12, 2^28], 50/50 uint32/uint64 keys, {args.budget_gb:g} GB budget, "
+                  "Radsort vs out-of-place",
         "value": r["keys_per_s"], "unit": "keys/s", "n_gpus": 1, "steps": args.requests,
         "warmup": 8, "ms_per_step": r["span_ms"] / args.requests, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
