@@ -48,7 +48,10 @@ extern "C" {
                                        radsort_last_stats() waits for them and reports */
 #define RADSORT_F_SHARED 4u         /* the GPU runs other work at the same time: use launch
                                        forms that need no co-resident grid (one workgroup
-                                       per tile, tiles claimed in order) */
+                                       per tile, tiles claimed in order).  Those forms are
+                                       taken anyway, being faster, by radsort_sort_pairs
+                                       with block_elems <= 1024 and always by
+                                       radsort_oop_sort_pairs */
 
 typedef struct radsort_opts {
     uint32_t block_elems;     /* b: block size in elements, a power of two in [64, 65536];

@@ -107,7 +107,9 @@ struct TileArgs {
 // (DYN = true): one workgroup per tile, launched normally, each claiming the next
 // tile from a counter; a tile is claimed only by a running workgroup, so every
 // lower tile is already claimed by one and the waits still end.  The dynamic form
-// needs no co-residency, so several sorts can share the GPU.
+// needs no co-residency, so several sorts can share the GPU; it also saves the
+// cooperative launch of every round, which makes it the faster form alone for
+// small blocks and for the out-of-place round.
 template <int KB, int VB, bool OOP, int FB, int SMAX, int WAVES, int ITEMS, bool DYN = false>
 __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
 {

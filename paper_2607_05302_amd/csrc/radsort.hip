@@ -1120,7 +1120,11 @@ int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes, int
     radsort_state* st = nullptr;
     rc = radsort_state_create(&st, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts);
     if (rc) return rc;
-    st->dynamic = opts && (opts->flags & RADSORT_F_SHARED);
+    // The launch form without co-residency (one workgroup per tile) is also the
+    // faster one alone for blocks of up to 1024 elements (no cooperative launch per
+    // round, which costs most at small n); with larger blocks the persistent form,
+    // whose workgroups overlap one tile's loads with the previous tile, is faster.
+    st->dynamic = (opts && (opts->flags & RADSORT_F_SHARED)) || g.b <= 1024;
     hipStream_t s = (hipStream_t)stream;
     const bool timing = opts && (opts->flags & RADSORT_F_TIMING);
     if (timing) g_timer.begin();
@@ -1170,7 +1174,9 @@ int radsort_oop_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
     }
     const bool timing = opts && (opts->flags & RADSORT_F_TIMING);
     if (timing) g_timer.begin();
-    const bool dyn = opts && (opts->flags & RADSORT_F_SHARED);
+    // the out-of-place round runs faster in the form without co-residency (one
+    // workgroup per tile) at every size and block tried, so it always takes it
+    const bool dyn = true;
     rc = dispatch<DoOop>(g.kb, g.vb, keys, payload, g, L, ws, dyn, s);
     g_timer.end();
     g_stats.timed = 0;
