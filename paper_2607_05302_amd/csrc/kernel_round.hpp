@@ -102,15 +102,21 @@ struct TileArgs {
 };
 
 
-// Two launch forms.  Persistent (DYN = false): a cooperative launch of as many
-// workgroups as are resident, each taking tiles in grid-stride order.  Dynamic
-// (DYN = true): one workgroup per tile, launched normally, each claiming the next
-// tile from a counter; a tile is claimed only by a running workgroup, so every
-// lower tile is already claimed by one and the waits still end.  The dynamic form
-// needs no co-residency, so several sorts can share the GPU; it also saves the
-// cooperative launch of every round, which makes it the faster form alone for
-// small blocks and for the out-of-place round.
-template <int KB, int VB, bool OOP, int FB, int SMAX, int WAVES, int ITEMS, bool DYN = false>
+// Three launch forms (DYN).  kPersistent: a cooperative launch of as many
+// workgroups as are resident, each taking tiles in grid-stride order.  kPerTile:
+// one workgroup per tile, launched normally, each claiming its tile from a
+// counter; a tile is claimed only by a running workgroup, so every lower tile is
+// already claimed by one and the waits still end.  kClaimLoop: a normal launch of
+// at most as many workgroups as fit, each claiming its next tile from the counter
+// while it works on the current one; a workgroup finishes its lower tile first, so
+// the lowest unfinished tile is always being worked on and depends only on finished
+// ones.  The last two need no co-residency, so several sorts can share the GPU, and
+// they save the cooperative launch of every round: measured alone, kPerTile is the
+// faster Radsort round for blocks of up to 1024 elements and kClaimLoop the faster
+// out-of-place round.
+constexpr int kPersistent = 0, kPerTile = 1, kClaimLoop = 2;
+
+template <int KB, int VB, bool OOP, int FB, int SMAX, int WAVES, int ITEMS, int DYN = kPersistent>
 __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
 {
     using K = typename UInt<KB>::T;
@@ -238,13 +244,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             if constexpr (VB != 0) vn[j] = valid ? *vp : (V)0;
         }
     };
-    uint32_t first_tile = blockIdx.x, step = gridDim.x;
-    if constexpr (DYN) {
-        __shared__ uint32_t claimed;
+    uint32_t first_tile = blockIdx.x;
+    __shared__ uint32_t claimed;  // the tile claimed next (claimed forms)
+    if constexpr (DYN != kPersistent) {
         if (tid == 0) claimed = add_agent(a.tile_ctr, 1u);
         __syncthreads();
         first_tile = claimed;
-        step = ntiles;  // one tile per workgroup
     }
     {
         uint32_t phys, len;
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     __syncthreads();
     load_tile(first_tile);
 
-    for (uint32_t tile = first_tile; tile < ntiles; tile += step) {
+    for (uint32_t tile = first_tile, next; tile < ntiles; tile = next) {
     K key[ITEMS];
     V val[ITEMS];
     uint32_t rk[ITEMS];  // wave-local rank << 12 | digit, or ~0 for an empty slot
@@ -264,7 +269,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
         if constexpr (VB != 0) val[j] = vn[j];
         rk[j] = vld[j] ? 0u : ~0u;
     }
+    if constexpr (DYN == kClaimLoop) {  // the next tile, one ahead: its loads overlap this one
+        if (tid == 0) claimed = add_agent(a.tile_ctr, 1u);
+    }
     __syncthreads();  // the previous tile is done with LDS
+    next = DYN == kClaimLoop ? claimed : DYN == kPerTile ? ntiles : tile + gridDim.x;
     for (uint32_t i = lane; i < SMAX; i += 64) wh[wave * SMAX + i] = 0;
     if constexpr (OR_RANK) {
         uint64_t* myor = (uint64_t*)lk + wave * SMAX;
@@ -273,7 +282,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     // the next tile's block info: loaded now, put in LDS when this tile is staged
     // (its loads are issued after that)
     uint32_t nx_phys, nx_len;
-    block_info_load(tile + step, nx_phys, nx_len);
+    block_info_load(next, nx_phys, nx_len);
 
     // Reuse of this tile's ring slot (see the look-back words above): the done
     // words of the tiles that must have finished are requested now and checked
@@ -411,7 +420,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     block_info_store(nx_phys, nx_len);
     __syncthreads();
     // registers are free again: issue the next tile's loads
-    load_tile(tile + step);
+    load_tile(next);
 
     uint32_t* base = wh;                  // per-digit data reusing the wave counts
     uint32_t* nfw = wh + SMAX;

@@ -365,12 +365,20 @@ void launch_super_counts(const Geo& g, const typename UInt<KB>::T* Ak,
                            pr);
 }
 
-// One workgroup per tile, claimed from a counter (no co-residency needed).
+// The claimed forms (no co-residency needed): one workgroup per tile, or for the
+// claim loop at most as many workgroups as fit at once.
 template <typename Args>
-int launch_dynamic(const void* kern, uint32_t tiles, uint32_t threads, Args& a, hipStream_t s)
+int launch_dynamic(const void* kern, uint32_t tiles, uint32_t threads, Args& a, hipStream_t s,
+                   bool loop)
 {
+    uint32_t grid = tiles;
+    if (loop) {
+        const int cap = resident_capacity(kern, threads);
+        if (cap <= 0) return RADSORT_E_DEVICE;
+        grid = std::min<uint32_t>(tiles, (uint32_t)cap);
+    }
     void* args[] = {(void*)&a};
-    RS_HIP(hipLaunchKernel(kern, dim3(tiles), dim3(threads), args, 0, s));
+    RS_HIP(hipLaunchKernel(kern, dim3(grid), dim3(threads), args, 0, s));
     return RADSORT_OK;
 }
 
@@ -382,17 +390,20 @@ int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = 
     const uint32_t tiles = OOP ? (uint32_t)((g.n + g.E - 1) / g.E) : g.tiles;
     if (tiles == 0) return RADSORT_OK;
     if (dyn) {
+        // measured alone: one workgroup per tile for the Radsort round, the claim
+        // loop for the out-of-place round
+        constexpr int M = OOP ? kClaimLoop : kPerTile;
         if (g.bits == 8)
             return launch_dynamic(
-                (const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS, true>, tiles,
-                64 * N::WAVES, a, s);
+                (const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS, M>, tiles,
+                64 * N::WAVES, a, s, OOP);
         if (g.bits < 8)
             return launch_dynamic(
-                (const void*)&k_round<KB, VB, OOP, 0, 256, N::WAVES, N::ITEMS, true>, tiles,
-                64 * N::WAVES, a, s);
+                (const void*)&k_round<KB, VB, OOP, 0, 256, N::WAVES, N::ITEMS, M>, tiles,
+                64 * N::WAVES, a, s, OOP);
         return launch_dynamic(
-            (const void*)&k_round<KB, VB, OOP, 0, 2048, Wd::WAVES, Wd::ITEMS, true>, tiles,
-            64 * Wd::WAVES, a, s);
+            (const void*)&k_round<KB, VB, OOP, 0, 2048, Wd::WAVES, Wd::ITEMS, M>, tiles,
+            64 * Wd::WAVES, a, s, OOP);
     }
     if (g.bits == 8)
         return launch_persistent((const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS>,
