@@ -401,7 +401,8 @@ def bench_serving(args):
         "warmup": 8, "ms_per_step": r["span_ms"] / args.requests, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",
         "config": {"workload": f"{args.requests} requests at {args.rate:g}/s offered "
-                               f"(splitmix64 seed {SERVE_SEED:#x}), budget {args.budget_gb:g} GB, "
+                               f"(arrivals and sizes: splitmix64 seed {SERVE_SEED:#x}; keys: torch's "
+                               f"device generator seeded per request), budget {args.budget_gb:g} GB, "
                                f"{args.slots} slots", "offered_rps": serve.offered_load(trace)},
         "radsort": r, "oop": res["oop"],
         "p99_ratio_oop_over_radsort": res["oop"]["p99_ms"] / r["p99_ms"],

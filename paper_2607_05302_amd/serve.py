@@ -11,7 +11,8 @@ Radsort admits about twice as much work.
 
 The sorts run with RADSORT_F_SHARED: their kernels need no co-resident grid, so
 several can share the GPU.  Inputs are drawn on the device when a request is
-admitted (the seeded streams of `workloads`), on the request's stream.
+admitted, on the request's stream (`draw_input`: torch's device generator seeded
+with the request's seed, one pass over the keys).
 
 Device memory: one buffer of the budget's size, allocated when the server starts,
 carved first-fit into one region per admitted request (keys, payload, workspace)
@@ -78,6 +79,26 @@ def footprint(req: Request, method: str, block: int = 1024) -> int:
     return region(req, method, block)[3]
 
 
+DRAW_CHUNK = 1 << 24  # keys per piece when drawing and checking inputs
+
+
+def draw_input(req: Request, keys, vals):
+    """Fills ``keys`` (int32 or int64, read as unsigned) with the request's input,
+    uniform over all bit patterns, and ``vals`` with 0 .. n-1, on the current
+    stream: torch's device generator seeded with the request's seed, drawn in
+    pieces of DRAW_CHUNK keys, so that the same request always gets the same keys
+    and a draw costs one pass over them."""
+    import torch
+    g = torch.Generator(device=keys.device)
+    g.manual_seed(req.seed & 0x7FFFFFFFFFFFFFFF)
+    lo_hi = (-(1 << 31), 1 << 31) if req.key_bytes == 4 else (-(1 << 63), (1 << 63) - 1)
+    for lo in range(0, req.n, DRAW_CHUNK):
+        hi = min(req.n, lo + DRAW_CHUNK)
+        torch.randint(*lo_hi, (hi - lo,), generator=g, dtype=keys.dtype, device=keys.device,
+                      out=keys[lo:hi])
+        torch.arange(lo, hi, dtype=torch.int32, device=vals.device, out=vals[lo:hi])
+
+
 class Arena:
     """First-fit allocation of byte ranges in [0, size): `alloc` returns the lowest
     offset of a free range that holds ``nbytes`` (rounded up to ALIGN), or None;
@@ -137,19 +158,13 @@ class Server:
         import torch
 
         import paper_2607_05302_amd as radsort
-        import workloads
         o_k, o_v, o_w, end = region(req, self.method, self.block)
         kdt = torch.int32 if req.key_bytes == 4 else torch.int64
         keys = self.buf[base + o_k: base + o_k + req.n * req.key_bytes].view(kdt)
         vals = self.buf[base + o_v: base + o_v + req.n * 4].view(torch.int32)
         ws = self.buf[base + o_w: base + end]
         with torch.cuda.stream(stream):
-            chunk = 1 << 24  # bounded temporaries: the input is drawn in pieces
-            for lo in range(0, req.n, chunk):
-                hi = min(req.n, lo + chunk)
-                keys[lo:hi] = workloads.uniform_t(req.seed, hi - lo, req.key_bytes, self.device,
-                                                  start=lo)
-                torch.arange(lo, hi, dtype=torch.int32, device=self.device, out=vals[lo:hi])
+            draw_input(req, keys, vals)
             sort = radsort.sort_ if self.method == "radsort" else radsort.oop_sort_
             sort(keys, vals, block_elems=self.block, stream=stream, workspace=ws, shared=True)
             done = torch.cuda.Event(enable_timing=True)
@@ -162,20 +177,24 @@ class Server:
         and the index payload summing to n (n - 1) / 2.  A check, not a proof: it
         catches lost, duplicated and misplaced records."""
         import torch
-        import workloads
         flip = torch.tensor(-(1 << 63), dtype=torch.int64, device=keys.device)
         unsorted = torch.zeros((), dtype=torch.int64, device=keys.device)
         ksum = torch.zeros((), dtype=torch.int64, device=keys.device)
         vsum = torch.zeros((), dtype=torch.int64, device=keys.device)
-        chunk = 1 << 24  # bounded temporaries; neighbouring chunks overlap by one key
-        for lo in range(0, req.n, chunk):
-            hi = min(req.n, lo + chunk)
+        # the input drawn again, piece by piece as draw_input draws it
+        k0 = torch.empty(min(req.n, DRAW_CHUNK), dtype=keys.dtype, device=keys.device)
+        g = torch.Generator(device=keys.device)
+        g.manual_seed(req.seed & 0x7FFFFFFFFFFFFFFF)
+        lo_hi = (-(1 << 31), 1 << 31) if req.key_bytes == 4 else (-(1 << 63), (1 << 63) - 1)
+        for lo in range(0, req.n, DRAW_CHUNK):  # neighbouring pieces overlap by one key
+            hi = min(req.n, lo + DRAW_CHUNK)
             k = keys[max(lo - 1, 0):hi]
             k = (k.to(torch.int64) & 0xFFFFFFFF) if req.key_bytes == 4 else k ^ flip
             unsorted += (k[1:] < k[:-1]).sum()
-            k0 = workloads.uniform_t(req.seed, hi - lo, req.key_bytes, self.device, start=lo)
-            ksum += k0.to(torch.int64).sum() - keys[lo:hi].to(torch.int64).sum()
-            vsum += vals[lo:hi].to(torch.int64).sum()
+            torch.randint(*lo_hi, (hi - lo,), generator=g, dtype=keys.dtype, device=keys.device,
+                          out=k0[:hi - lo])
+            ksum += k0[:hi - lo].sum(dtype=torch.int64) - keys[lo:hi].sum(dtype=torch.int64)
+            vsum += vals[lo:hi].sum(dtype=torch.int64)
         return (int(unsorted.item()) == 0 and int(ksum.item()) == 0
                 and int(vsum.item()) == req.n * (req.n - 1) // 2)
 

@@ -5,7 +5,6 @@ import numpy as np
 import pytest
 
 import oracle
-import workloads
 
 torch = pytest.importorskip("torch")
 import paper_2607_05302_amd as radsort  # noqa: E402
@@ -15,9 +14,16 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
+def drawn(req):
+    """The request's input as the server draws it."""
+    keys = torch.empty(req.n, dtype=torch.int32 if req.key_bytes == 4 else torch.int64, device=DEV)
+    vals = torch.empty(req.n, dtype=torch.int32, device=DEV)
+    serve.draw_input(req, keys, vals)
+    return keys, vals
+
+
 def alone(req):
-    keys = workloads.uniform_t(req.seed, req.n, req.key_bytes, DEV)
-    vals = torch.arange(req.n, dtype=torch.int32, device=DEV)
+    keys, vals = drawn(req)
     radsort.sort_(keys, vals, check=True)
     return keys.cpu().numpy(), vals.cpu().numpy()
 
@@ -36,7 +42,7 @@ def test_results_alone_and_in_the_mix(method):
         assert np.array_equal(mk, ak), f"keys of request {r.rid} differ"
         assert np.array_equal(mv, av), f"payload of request {r.rid} differs"
         if r.n <= 1 << 16:
-            src = workloads.uniform_t(r.seed, r.n, r.key_bytes, "cpu").numpy()
+            src = drawn(r)[0].cpu().numpy()
             src = src.view(np.uint32 if r.key_bytes == 4 else np.uint64)
             ok, ov = oracle.radsort(src, np.arange(r.n, dtype=np.uint32), 256,
                                     r.key_bytes, 1024)
@@ -48,8 +54,7 @@ def test_results_alone_and_in_the_mix(method):
 @pytest.mark.parametrize("n,kb", [(3_000_001, 8), (5_000_000, 4)])
 def test_workspace_error_reads_clear_after_shared_sorts(method, n, kb):
     req = serve.Request(0, 0.0, n, kb, 0x77 + n)
-    keys = workloads.uniform_t(req.seed, n, kb, DEV)
-    vals = torch.arange(n, dtype=torch.int32, device=DEV)
+    keys, vals = drawn(req)
     wsb = (radsort.workspace_bytes if method == "radsort" else radsort.oop_workspace_bytes)(
         n, kb, 4, 8, 1024)
     ws = torch.full((wsb,), 0xFF, dtype=torch.uint8, device=DEV)

@@ -75,3 +75,20 @@ def test_arena_random_against_a_byte_map():
                 owned[off // 256: off // 256 + units] = True
                 held.append((off, nb))
         assert a.free_bytes() == (64 - owned.sum()) * 256
+
+
+def test_draw_input_is_seeded_and_covers_the_key_range():
+    import torch
+    for kb, dt in [(4, torch.int32), (8, torch.int64)]:
+        n = serve.DRAW_CHUNK + 1000  # two pieces
+        r = serve.Request(0, 0.0, n, kb, 12345)
+        a, av = torch.empty(n, dtype=dt), torch.empty(n, dtype=torch.int32)
+        b, bv = torch.empty(n, dtype=dt), torch.empty(n, dtype=torch.int32)
+        serve.draw_input(r, a, av)
+        serve.draw_input(r, b, bv)
+        assert torch.equal(a, b) and torch.equal(av, torch.arange(n, dtype=torch.int32))
+        c, cv = torch.empty(n, dtype=dt), torch.empty(n, dtype=torch.int32)
+        serve.draw_input(serve.Request(0, 0.0, n, kb, 12346), c, cv)
+        assert not torch.equal(a, c)
+        assert (a < 0).any() and (a > 0).any()  # both halves of the unsigned range
+        assert a.unique().numel() > 0.99 * n
