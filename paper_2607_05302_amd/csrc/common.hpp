@@ -84,6 +84,14 @@ __device__ __forceinline__ bool spin_give_up(uint32_t spins, uint32_t* err)
     return (spins & 255u) == 0 && ld_agent(err) != 0;
 }
 
+// A store through a pointer known to address global memory (the generic pointer
+// would compile to a flat store, which also waits on the LDS counter).
+template <typename X>
+__device__ __forceinline__ void st_global(X* p, X v)
+{
+    *(__attribute__((address_space(1))) X*)p = v;
+}
+
 // --- blocks (Eq. 1): physical index j < 2 sigma lives in T, the rest overlays A ---
 
 template <typename X>

@@ -52,6 +52,8 @@
 // the sequential algorithm.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace rs {
@@ -116,11 +118,27 @@ struct TileArgs {
 // out-of-place round.
 constexpr int kPersistent = 0, kPerTile = 1, kClaimLoop = 2;
 
-template <int KB, int VB, bool OOP, int FB, int SMAX, int WAVES, int ITEMS, int DYN = kPersistent>
-__global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
+// Shape of a round's workgroup (see TileCfg in radsort.hip): WAVES waves of 64
+// lanes with ITEMS slots each; PF: the next tile's records are loaded into
+// registers while the current tile is processed (for one workgroup per CU);
+// SPLIT: the payload is staged in LDS only after the keys have been scattered,
+// in the same LDS, which halves the staging area so that more workgroups fit on
+// a CU; OCC: waves per SIMD the register allocation must allow.
+template <int WAVES_, int ITEMS_, bool PF_, bool SPLIT_, int OCC_> struct RoundShape {
+    static constexpr int WAVES = WAVES_, ITEMS = ITEMS_, OCC = OCC_;
+    static constexpr bool PF = PF_, SPLIT = SPLIT_;
+};
+
+template <int KB, int VB, bool OOP, int FB, int SMAX, class SH, int DYN = kPersistent>
+__global__ __launch_bounds__(SH::WAVES * 64)
+__attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
 {
     using K = typename UInt<KB>::T;
     using V = typename Payload<VB>::T;
+    constexpr int WAVES = SH::WAVES, ITEMS = SH::ITEMS;
+    constexpr bool PF = SH::PF;
+    constexpr bool OR_RANK_ = SMAX <= 256;
+    constexpr bool SPLIT = SH::SPLIT && VB != 0 && OR_RANK_;  // two-pass staging
     constexpr int NT = WAVES * 64;
     constexpr int E = NT * ITEMS;
     constexpr int SEG = E / WAVES;
@@ -139,8 +157,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     const uint32_t log2b = a.log2b, b = 1u << log2b, two_sigma = 2 * sigma;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    __shared__ K lk[E];                          // keys in (digit, slot) order; OR tables before
-    __shared__ V lv[VB ? E : 1];                 // payload in the same order
+    // keys in (digit, slot) order (OR tables before); with SPLIT the payload
+    // follows in the same bytes once the keys are written out
+    constexpr int SB = SPLIT ? (KB > VB ? KB : VB) : KB;
+    __shared__ __align__(16) unsigned char stage[E * SB];
+    K* lk = (K*)stage;
+    __shared__ V lv_[(VB && !SPLIT) ? E : 1];    // payload in the same order (no SPLIT)
+    V* lv = SPLIT ? (V*)stage : lv_;
     __shared__ __align__(16) uint32_t uni[UNI];  // slots + cnt + excl, later the pointer table
     __shared__ __align__(16) uint32_t wh[WAVES * SMAX];  // per-wave counts, later per-digit data
     __shared__ uint32_t tbo[SMAX];
@@ -257,18 +280,25 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
         block_info_store(phys, len);
     }
     __syncthreads();
-    load_tile(first_tile);
+    if constexpr (PF) load_tile(first_tile);
 
     for (uint32_t tile = first_tile, next; tile < ntiles; tile = next) {
+    // without PF the tile's loads are issued here; its block info is in LDS
+    if constexpr (!PF) load_tile(tile);
     K key[ITEMS];
     V val[ITEMS];
     uint32_t rk[ITEMS];  // wave-local rank << 12 | digit, or ~0 for an empty slot
+    bool allv = true;
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         key[j] = kn[j];
         if constexpr (VB != 0) val[j] = vn[j];
         rk[j] = vld[j] ? 0u : ~0u;
+        allv = allv && vld[j];
     }
+    // every slot of the wave holds an element (all but a few waves of a round):
+    // the per-item checks below are left out
+    const bool wfull = ballot(!allv) == 0;
     if constexpr (DYN == kClaimLoop) {  // the next tile, one ahead: its loads overlap this one
         if (tid == 0) claimed = add_agent(a.tile_ctr, 1u);
     }
@@ -300,21 +330,25 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     if constexpr (OR_RANK) {
         uint64_t* myor = (uint64_t*)lk + wave * SMAX;
         const uint64_t mybit = 1ull << lane;
+        auto or_rank = [&](auto full) {
 #pragma unroll
-        for (int j = 0; j < ITEMS; j++) {
-            if (rk[j] != ~0u) {
-                const uint32_t d = (uint32_t)(key[j] >> a.shift) & dmask;
-                __hip_atomic_fetch_or(myor + d, mybit, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_WORKGROUP);
-                const uint64_t peers = myor[d];
-                const uint32_t old = myh[d];
-                if ((peers >> lane) == 1ull) {  // highest lane of the set: commit
-                    myh[d] = old + (uint32_t)__popcll(peers);
-                    myor[d] = 0;
+            for (int j = 0; j < ITEMS; j++) {
+                if (full.value || rk[j] != ~0u) {
+                    const uint32_t d = (uint32_t)(key[j] >> a.shift) & dmask;
+                    __hip_atomic_fetch_or(myor + d, mybit, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const uint64_t peers = myor[d];
+                    const uint32_t old = myh[d];
+                    if ((peers >> lane) == 1ull) {  // highest lane of the set: commit
+                        myh[d] = old + (uint32_t)__popcll(peers);
+                        myor[d] = 0;
+                    }
+                    rk[j] = ((old + popc_below(peers)) << 12) | d;
                 }
-                rk[j] = ((old + popc_below(peers)) << 12) | d;
             }
-        }
+        };
+        if (wfull) or_rank(std::true_type{});
+        else or_rank(std::false_type{});
     } else {
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
@@ -407,20 +441,26 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     __syncthreads();
 
     // ---- stage in (digit, slot) order ------------------------------------------------
+    // (with SPLIT, rk[j] keeps the staged position for the payload pass)
+    auto stage_items = [&](auto full) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; j++) {
-        if (rk[j] != ~0u) {
-            const uint32_t d = rk[j] & 0xFFFu;
-            const uint32_t p = wh[wave * SMAX + d] + (rk[j] >> 12);
-            lk[p] = key[j];
-            if constexpr (VB != 0) lv[p] = val[j];
-            ls[p] = (uint16_t)(wave * SEG + j * 64 + lane);
+        for (int j = 0; j < ITEMS; j++) {
+            if (full.value || rk[j] != ~0u) {
+                const uint32_t d = rk[j] & 0xFFFu;
+                const uint32_t p = wh[wave * SMAX + d] + (rk[j] >> 12);
+                lk[p] = key[j];
+                if constexpr (VB != 0 && !SPLIT) lv[p] = val[j];
+                ls[p] = (uint16_t)(wave * SEG + j * 64 + lane);
+                if constexpr (SPLIT) rk[j] = p;
+            }
         }
-    }
+    };
+    if (wfull) stage_items(std::true_type{});
+    else stage_items(std::false_type{});
     block_info_store(nx_phys, nx_len);
     __syncthreads();
     // registers are free again: issue the next tile's loads
-    load_tile(next);
+    if constexpr (PF) load_tile(next);
 
     uint32_t* base = wh;                  // per-digit data reusing the wave counts
     uint32_t* nfw = wh + SMAX;
@@ -469,15 +509,47 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
     if constexpr (OOP) {
         for (uint32_t d = tid; d < sigma; d += NT) dt[d].x = a.est[d] + base[d] - excl[d];
         __syncthreads();
-        for (uint32_t p = tid; p < total; p += NT) {
-            const K k = lk[p];
-            const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
-            const uint64_t pos = (uint64_t)p + dt[d].x;
-            if (pos < a.n) {
-                a.Tk[pos] = k;
-                if constexpr (VB != 0) a.Tv[pos] = lv[p];
-            } else {  // never for consistent digit starts
-                raise_error(a.err, kErrBounds);
+        if constexpr (SPLIT) {
+            // keys first, remembering each position's destination; then the
+            // payload is staged in the same LDS and written to the same places
+            uint32_t dst[ITEMS];
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                const uint32_t p = tid + i * NT;
+                dst[i] = ~0u;
+                if (p < total) {
+                    const K k = lk[p];
+                    const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
+                    const uint64_t pos = (uint64_t)p + dt[d].x;
+                    if (pos < a.n) {
+                        a.Tk[pos] = k;
+                        dst[i] = (uint32_t)pos;
+                    } else {  // never for consistent digit starts
+                        raise_error(a.err, kErrBounds);
+                    }
+                }
+            }
+            __syncthreads();  // every staged key was read
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++)
+                if (rk[j] != ~0u) lv[rk[j]] = val[j];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; i++) {
+                const uint32_t p = tid + i * NT;
+                if (dst[i] != ~0u) a.Tv[dst[i]] = lv[p];
+            }
+        } else {
+            for (uint32_t p = tid; p < total; p += NT) {
+                const K k = lk[p];
+                const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
+                const uint64_t pos = (uint64_t)p + dt[d].x;
+                if (pos < a.n) {
+                    a.Tk[pos] = k;
+                    if constexpr (VB != 0) a.Tv[pos] = lv[p];
+                } else {  // never for consistent digit starts
+                    raise_error(a.err, kErrBounds);
+                }
             }
         }
     } else {
@@ -635,15 +707,63 @@ __global__ __launch_bounds__(WAVES * 64) void k_round(TileArgs<KB, VB> a)
             }
             __syncthreads();
             // ---- scatter ------------------------------------------------------------
-            for (uint32_t p = tid; p < total; p += NT) {
-                const K k = lk[p];
-                const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
-                const uint2 x = dt[d];
-                const uint32_t r = p + x.x;
-                const uint32_t e = x.y + (r >> log2b);
-                const uint32_t off = r & (b - 1);
-                ((K*)(uintptr_t)ptab[2 * e])[off] = k;
-                if constexpr (VB != 0) ((V*)(uintptr_t)ptab[2 * e + 1])[off] = lv[p];
+            if constexpr (SPLIT) {
+                // keys first, remembering (table entry, offset) of each position;
+                // then the payload is staged in the same LDS and follows its key
+                uint32_t dst[ITEMS];
+                const bool tfull = total == (uint32_t)E;  // the same for the workgroup
+                auto scatter_keys = [&](auto full) {
+#pragma unroll
+                    for (int i = 0; i < ITEMS; i++) {
+                        const uint32_t p = tid + i * NT;
+                        dst[i] = ~0u;
+                        if (full.value || p < total) {
+                            const K k = lk[p];
+                            const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
+                            const uint2 x = dt[d];
+                            const uint32_t r = p + x.x;
+                            const uint32_t e = x.y + (r >> log2b);
+                            const uint32_t off = r & (b - 1);
+                            st_global((K*)(uintptr_t)ptab[2 * e] + off, k);
+                            dst[i] = e << 16 | off;  // e < TBL < 2^16, off < b <= 2^16
+                        }
+                    }
+                };
+                if (tfull) scatter_keys(std::true_type{});
+                else scatter_keys(std::false_type{});
+                __syncthreads();  // every staged key was read
+                if (wfull) {
+#pragma unroll
+                    for (int j = 0; j < ITEMS; j++) lv[rk[j]] = val[j];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < ITEMS; j++)
+                        if (rk[j] != ~0u) lv[rk[j]] = val[j];
+                }
+                __syncthreads();
+                auto scatter_vals = [&](auto full) {
+#pragma unroll
+                    for (int i = 0; i < ITEMS; i++) {
+                        const uint32_t p = tid + i * NT;
+                        if (full.value || dst[i] != ~0u)
+                            st_global((V*)(uintptr_t)ptab[2 * (dst[i] >> 16) + 1] +
+                                          (dst[i] & 0xFFFFu),
+                                      lv[p]);
+                    }
+                };
+                if (tfull) scatter_vals(std::true_type{});
+                else scatter_vals(std::false_type{});
+            } else {
+                for (uint32_t p = tid; p < total; p += NT) {
+                    const K k = lk[p];
+                    const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
+                    const uint2 x = dt[d];
+                    const uint32_t r = p + x.x;
+                    const uint32_t e = x.y + (r >> log2b);
+                    const uint32_t off = r & (b - 1);
+                    st_global((K*)(uintptr_t)ptab[2 * e] + off, k);
+                    if constexpr (VB != 0) st_global((V*)(uintptr_t)ptab[2 * e + 1] + off, lv[p]);
+                }
             }
         } else {
             // wide digits: the pointer table would not fit in LDS

@@ -39,7 +39,7 @@ radsort_stats g_stats{};
     } while (0)
 
 constexpr uint32_t kRingWords = 1u << 19;  // look-back ring: 2^ring_log2 * sigma count words
-constexpr uint32_t kSuperLog2 = 3;         // tiles per super-tile: 8, or enough to hold a block
+constexpr uint32_t kSuperSlotsLog2 = 16;   // slots per super-tile: 2^16 (8 tiles of 8192)
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -55,9 +55,36 @@ int ilog2(uint64_t x)
 // element; the staged tile and the per-wave digit counts must fit in LDS (one
 // workgroup of up to 110 KB per CU), and the next tile's records, held in
 // registers while the current one is processed, must fit the register file.
-template <int KB, int VB, bool WIDE> struct TileCfg {
-    static constexpr int WAVES = WIDE ? 4 : 8;
-    static constexpr int ITEMS = (KB + VB >= 12) ? 8 : 16;
+// Shape of the round kernel's workgroup per record size (KB key bytes, VB payload
+// bytes), digit width (WIDE: more than 8 bits) and round (OOP: Alg. 1).  E = 64 *
+// WAVES * ITEMS slots per tile.  The shape decides how many workgroups share a
+// compute unit: the staged tile and per-wave digit counts must fit its 160 KB of
+// LDS, the records held in registers its register file.
+//   shape 0: one workgroup per CU, the next tile's records loaded into registers
+//     while the current one is processed (PF), the payload staged beside the keys;
+//   shape 1: two workgroups per CU (at most 128 VGPRs and about 68 KB of LDS
+//     each): no register prefetch, the payload staged after the keys are written
+//     out (SPLIT).  Measured at 2^28 uint32 + uint32, b = 2048: Radsort round
+//     1.59 ms against 2.07 ms for shape 0, with one workgroup per tile;
+//   shapes 2-4 (tiles of 4096 slots, two to three workgroups per CU) measured
+//     slower (2.05-2.21 ms) and are kept for measurement only.
+// The out-of-place round keeps shape 0 (1.50 ms, against 2.36 ms with shape 1).
+#ifndef RS_ROUND_CFG
+#define RS_ROUND_CFG 1
+#endif
+template <int KB, int VB, bool WIDE, bool OOP = false> struct TileCfg {
+    static constexpr int C = (WIDE || OOP) ? 0 : RS_ROUND_CFG;
+    static constexpr bool BIG = KB + VB >= 12;
+    static constexpr bool NARROW = KB == 4 && VB <= 4;  // 8 bytes or less per record
+    static constexpr int WAVES = WIDE ? 4 : (C == 3 ? 4 : 8);
+    static constexpr int ITEMS = C == 0 ? (BIG ? 8 : 16)
+                               : C == 1 ? (NARROW ? 16 : 8)
+                               : C == 3 ? (BIG ? 8 : 16)
+                                        : 8;
+    static constexpr bool PF = C == 0 || C == 4;
+    static constexpr bool SPLIT = C != 0;
+    static constexpr int OCC = C == 0 ? 1 : C == 2 ? 6 : 4;
+    using Shape = RoundShape<WAVES, ITEMS, PF, SPLIT, OCC>;
     static constexpr int E = 64 * WAVES * ITEMS;
 };
 
@@ -68,6 +95,7 @@ struct Geo {
     uint32_t npi = 0, E = 0, tiles = 0, ring_w = 0, ring_log2 = 0;
     uint32_t st_log2 = 0;                 // tiles per super-tile: 2^st_log2
     uint32_t supers = 0, oop_supers = 0;  // super-tiles of a Radsort / out-of-place round
+    uint32_t oop_E = 0, oop_st_log2 = 0;  // tile and super-tile of the out-of-place round
 };
 
 // Workspace regions (byte offsets), each 256-byte aligned.
@@ -77,20 +105,21 @@ struct Layout {
     uint64_t ring_bytes, fin_bytes, total;
 };
 
-template <bool WIDE> uint32_t tile_elems_t(uint32_t kb, uint32_t vb)
+template <bool WIDE, bool OOP> uint32_t tile_elems_t(uint32_t kb, uint32_t vb)
 {
-    if (kb == 4 && vb == 0) return TileCfg<4, 0, WIDE>::E;
-    if (kb == 4 && vb == 4) return TileCfg<4, 4, WIDE>::E;
-    if (kb == 4 && vb == 8) return TileCfg<4, 8, WIDE>::E;
-    if (kb == 8 && vb == 0) return TileCfg<8, 0, WIDE>::E;
-    if (kb == 8 && vb == 4) return TileCfg<8, 4, WIDE>::E;
-    return TileCfg<8, 8, WIDE>::E;
+    if (kb == 4 && vb == 0) return TileCfg<4, 0, WIDE, OOP>::E;
+    if (kb == 4 && vb == 4) return TileCfg<4, 4, WIDE, OOP>::E;
+    if (kb == 4 && vb == 8) return TileCfg<4, 8, WIDE, OOP>::E;
+    if (kb == 8 && vb == 0) return TileCfg<8, 0, WIDE, OOP>::E;
+    if (kb == 8 && vb == 4) return TileCfg<8, 4, WIDE, OOP>::E;
+    return TileCfg<8, 8, WIDE, OOP>::E;
 }
 
 // digits of more than 8 bits take the wide tile (per-wave counts of 2^11 digits)
-uint32_t tile_elems(uint32_t kb, uint32_t vb, uint32_t bits)
+uint32_t tile_elems(uint32_t kb, uint32_t vb, uint32_t bits, bool oop)
 {
-    return bits > 8 ? tile_elems_t<true>(kb, vb) : tile_elems_t<false>(kb, vb);
+    if (bits > 8) return oop ? tile_elems_t<true, true>(kb, vb) : tile_elems_t<true, false>(kb, vb);
+    return oop ? tile_elems_t<false, true>(kb, vb) : tile_elems_t<false, false>(kb, vb);
 }
 
 int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bits,
@@ -116,7 +145,8 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     // pi entries are 32-bit with the top bit free; finalize scans at most 4096^2 entries
     if (npi >= (uint64_t)kScanTile * kScanTile) return RADSORT_E_UNSUPPORTED;
     g.npi = (uint32_t)npi;
-    g.E = tile_elems(g.kb, g.vb, g.bits);
+    g.E = tile_elems(g.kb, g.vb, g.bits, false);
+    g.oop_E = tile_elems(g.kb, g.vb, g.bits, true);
     // input slots of a round: at most (floor(n/b) + sigma) blocks of b
     uint64_t slots = (g.nb + g.sigma) << g.log2b;
     g.tiles = (uint32_t)((slots + g.E - 1) / g.E);
@@ -127,11 +157,17 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     while (ring_w < g.tiles && ring_w < ring_cap) ring_w <<= 1;
     g.ring_w = ring_w;
     g.ring_log2 = ilog2(g.ring_w);
-    g.st_log2 = std::max<uint32_t>(kSuperLog2, g.log2b > (uint32_t)ilog2(g.E)
-                                                   ? g.log2b - (uint32_t)ilog2(g.E) : 0u);
+    // a super-tile spans at least 2^kSuperSlotsLog2 slots and at least one block
+    auto super_log2 = [&](uint32_t E) {
+        const uint32_t elog = (uint32_t)ilog2(E);
+        return std::max<uint32_t>(kSuperSlotsLog2 > elog ? kSuperSlotsLog2 - elog : 0u,
+                                  g.log2b > elog ? g.log2b - elog : 0u);
+    };
+    g.st_log2 = super_log2(g.E);
     g.supers = (g.tiles + (1u << g.st_log2) - 1) >> g.st_log2;
-    const uint64_t oop_tiles = (n + g.E - 1) / g.E;
-    g.oop_supers = (uint32_t)((oop_tiles + (1u << g.st_log2) - 1) >> g.st_log2);
+    g.oop_st_log2 = super_log2(g.oop_E);
+    const uint64_t oop_tiles = (n + g.oop_E - 1) / g.oop_E;
+    g.oop_supers = (uint32_t)((oop_tiles + (1u << g.oop_st_log2) - 1) >> g.oop_st_log2);
     return RADSORT_OK;
 }
 
@@ -350,7 +386,8 @@ void launch_super_counts(const Geo& g, const typename UInt<KB>::T* Ak,
                          uint32_t r, PlanPtrs p, hipStream_t s)
 {
     const uint32_t rows = (OOP ? g.oop_supers : g.supers) + 1;
-    const uint32_t sts_log2 = g.st_log2 + (uint32_t)ilog2(g.E);
+    const uint32_t sts_log2 = OOP ? g.oop_st_log2 + (uint32_t)ilog2(g.oop_E)
+                                  : g.st_log2 + (uint32_t)ilog2(g.E);
     const uint32_t sig = g.sigma, plan = OOP ? 2u : 1u;
     PlanPtrs pr{p.S + r * sig, p.Pidx + (r + 1) * sig, p.Plen + (r + 1) * sig, p.f + r + 1,
                 p.est + r * sig};
@@ -385,33 +422,40 @@ int launch_dynamic(const void* kern, uint32_t tiles, uint32_t threads, Args& a, 
 template <int KB, int VB, bool OOP>
 int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = false)
 {
-    using N = TileCfg<KB, VB, false>;
-    using Wd = TileCfg<KB, VB, true>;
-    const uint32_t tiles = OOP ? (uint32_t)((g.n + g.E - 1) / g.E) : g.tiles;
+    using N = TileCfg<KB, VB, false, OOP>;
+    using Wd = TileCfg<KB, VB, true, OOP>;
+    const uint32_t tiles = OOP ? (uint32_t)((g.n + g.oop_E - 1) / g.oop_E) : g.tiles;
     if (tiles == 0) return RADSORT_OK;
+    // shapes without register prefetch take a workgroup per tile (the persistent
+    // form would hold the loop's state in registers the shape does not have)
+    if (g.bits <= 8 && !N::PF) dyn = true;
     if (dyn) {
         // measured alone: one workgroup per tile for the Radsort round, the claim
         // loop for the out-of-place round
         constexpr int M = OOP ? kClaimLoop : kPerTile;
         if (g.bits == 8)
             return launch_dynamic(
-                (const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS, M>, tiles,
+                (const void*)&k_round<KB, VB, OOP, 8, 256, typename N::Shape, M>, tiles,
                 64 * N::WAVES, a, s, OOP);
         if (g.bits < 8)
             return launch_dynamic(
-                (const void*)&k_round<KB, VB, OOP, 0, 256, N::WAVES, N::ITEMS, M>, tiles,
+                (const void*)&k_round<KB, VB, OOP, 0, 256, typename N::Shape, M>, tiles,
                 64 * N::WAVES, a, s, OOP);
         return launch_dynamic(
-            (const void*)&k_round<KB, VB, OOP, 0, 2048, Wd::WAVES, Wd::ITEMS, M>, tiles,
+            (const void*)&k_round<KB, VB, OOP, 0, 2048, typename Wd::Shape, M>, tiles,
             64 * Wd::WAVES, a, s, OOP);
     }
-    if (g.bits == 8)
-        return launch_persistent((const void*)&k_round<KB, VB, OOP, 8, 256, N::WAVES, N::ITEMS>,
-                                 tiles, 64 * N::WAVES, a, s);
-    if (g.bits < 8)
-        return launch_persistent((const void*)&k_round<KB, VB, OOP, 0, 256, N::WAVES, N::ITEMS>,
-                                 tiles, 64 * N::WAVES, a, s);
-    return launch_persistent((const void*)&k_round<KB, VB, OOP, 0, 2048, Wd::WAVES, Wd::ITEMS>,
+    if constexpr (N::PF) {
+        if (g.bits == 8)
+            return launch_persistent(
+                (const void*)&k_round<KB, VB, OOP, 8, 256, typename N::Shape>, tiles,
+                64 * N::WAVES, a, s);
+        if (g.bits < 8)
+            return launch_persistent(
+                (const void*)&k_round<KB, VB, OOP, 0, 256, typename N::Shape>, tiles,
+                64 * N::WAVES, a, s);
+    }
+    return launch_persistent((const void*)&k_round<KB, VB, OOP, 0, 2048, typename Wd::Shape>,
                              tiles, 64 * Wd::WAVES, a, s);
 }
 
@@ -626,7 +670,7 @@ template <int KB, int VB> struct Ops {
             a.bits = g.bits;
             a.log2b = g.log2b;
             a.ring_log2 = g.ring_log2;
-            a.st_log2 = g.st_log2;
+            a.st_log2 = g.oop_st_log2;
             uint32_t* stcnt = (uint32_t*)(ws + L.stcnt);
             a.stbase = stcnt;
             launch_fill((uint32_t*)a.agg, L.ring_bytes / 4, 0, s);
