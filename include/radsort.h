@@ -52,6 +52,15 @@ extern "C" {
                                        taken anyway, being faster, by radsort_sort_pairs
                                        with block_elems <= 1024 and always by
                                        radsort_oop_sort_pairs */
+#define RADSORT_F_SEQ_DRAWS 8u      /* Radsort rounds draw their blocks in the order of the
+                                       sequential scan of Alg. 5 (the elements that fill
+                                       the blocks, in input order), so that pi after every
+                                       round equals the sequential algorithm's.  Without it
+                                       the draws of one tile go in (digit, block) order:
+                                       the same pool entries per tile (Lemma 1 holds alike),
+                                       the same P, f and logical contents, a different pi;
+                                       faster.  Digits of more than 8 bits always draw in
+                                       the sequential order */
 
 typedef struct radsort_opts {
     uint32_t block_elems;     /* b: block size in elements, a power of two in [64, 65536];

@@ -21,7 +21,7 @@ import os
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libradsort.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_TIMEOUT = 0, -1, -2, -3, -4, -5
-F_CHECK, F_TIMING, F_SHARED = 1, 2, 4
+F_CHECK, F_TIMING, F_SHARED, F_SEQ_DRAWS = 1, 2, 4, 8
 MAX_ROUNDS = 64
 
 # every function declared in include/radsort.h
@@ -177,12 +177,13 @@ def oop_workspace_bytes(n, key_bytes=4, payload_bytes=0, digit_bits=8, block_ele
 
 
 def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, workspace=None,
-          check=False, timing=False, shared=False):
+          check=False, timing=False, shared=False, seq_draws=False):
     """Radsort in place on the current stream (radsort_sort_pairs).  shared: other
-    work runs on the GPU at the same time (RADSORT_F_SHARED)."""
+    work runs on the GPU at the same time (RADSORT_F_SHARED); seq_draws: blocks are
+    drawn in the sequential algorithm's order (RADSORT_F_SEQ_DRAWS)."""
     kb, vb = _validate(keys, payload)
     o = _opts(block_elems, workspace, (F_CHECK if check else 0) | (F_TIMING if timing else 0)
-              | (F_SHARED if shared else 0))
+              | (F_SHARED if shared else 0) | (F_SEQ_DRAWS if seq_draws else 0))
     with _device(keys):
         rc = load().radsort_sort_pairs(
             ctypes.c_void_p(keys.data_ptr()),
@@ -336,11 +337,12 @@ class _device:
 class State:
     """The step interface: setup, rounds, finalize, and inspection between them."""
 
-    def __init__(self, keys, payload=None, digit_bits=8, block_elems=1024, workspace=None):
+    def __init__(self, keys, payload=None, digit_bits=8, block_elems=1024, workspace=None,
+                 seq_draws=False):
         kb, vb = _validate(keys, payload)
         self.keys, self.payload = keys, payload
         self.kb, self.vb, self.digit_bits = kb, vb, digit_bits
-        o = _opts(block_elems, workspace)
+        o = _opts(block_elems, workspace, F_SEQ_DRAWS if seq_draws else 0)
         h = ctypes.c_void_p()
         with _device(keys):
             rc = load().radsort_state_create(

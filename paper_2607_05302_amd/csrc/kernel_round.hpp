@@ -101,7 +101,25 @@ struct TileArgs {
     uint32_t* tile_ctr;      // dynamic launches: next tile to claim, zero on entry
     uint32_t shift, bits, log2b, npi, ring_log2;
     uint32_t st_log2;        // tiles per super-tile: 2^st_log2
+    uint64_t* tl;            // timeline builds only: kTlStamps stamps per tile, or null
 };
+
+// Timeline builds (RS_TIMELINE defined): thread 0 of each workgroup records the
+// 100 MHz real-time counter at the phase boundaries of every tile, so that a
+// profiling run can attribute the round's time to its steps.  Normal builds
+// record nothing.
+constexpr int kTlStamps = 16;
+#ifdef RS_TIMELINE
+#define RS_STAMP(k)                                                                       \
+    do {                                                                                  \
+        if (threadIdx.x == 0 && a.tl)                                                     \
+            a.tl[(uint64_t)tile * kTlStamps + (k)] = __builtin_amdgcn_s_memrealtime();    \
+    } while (0)
+#else
+#define RS_STAMP(k) \
+    do {            \
+    } while (0)
+#endif
 
 
 // Three launch forms (DYN).  kPersistent: a cooperative launch of as many
@@ -129,7 +147,14 @@ template <int WAVES_, int ITEMS_, bool PF_, bool SPLIT_, int OCC_> struct RoundS
     static constexpr bool PF = PF_, SPLIT = SPLIT_;
 };
 
-template <int KB, int VB, bool OOP, int FB, int SMAX, class SH, int DYN = kPersistent>
+// SEQ: a tile's draws take their pool entries in the slot order of the elements
+// that fill the blocks, as the sequential scan of Alg. 5 does, so that pi after
+// every round equals the sequential algorithm's.  Otherwise in (digit, block)
+// order: each tile still draws the same pool entries, only their assignment to
+// the tile's filled blocks differs, and the slot of every staged element need
+// not be kept.
+template <int KB, int VB, bool OOP, int FB, int SMAX, class SH, int DYN = kPersistent,
+          bool SEQ = true>
 __global__ __launch_bounds__(SH::WAVES * 64)
 __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
 {
@@ -146,7 +171,8 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
     constexpr int TBL = MAXBLK + 2 * SMAX;        // blocks one tile can write
     constexpr bool OR_RANK = SMAX <= 256;         // OR-table ranking fits in LDS
     constexpr int PTAB = OR_RANK ? 4 * TBL : 0;  // words of the pointer table
-    constexpr int UNI = (E / 2 + 2 * SMAX) > PTAB ? (E / 2 + 2 * SMAX) : PTAB;
+    constexpr int LSW = SEQ ? E / 2 : 0;          // words of the slot array
+    constexpr int UNI = (LSW + 2 * SMAX) > PTAB ? (LSW + 2 * SMAX) : PTAB;
     static_assert(E <= 65536, "slot indices are 16-bit");
     static_assert((E & (E - 1)) == 0, "tiles and super-tiles are powers of two");
     static_assert(WAVES >= 4, "per-digit scratch reuses the per-wave counts");
@@ -166,16 +192,24 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
     V* lv = SPLIT ? (V*)stage : lv_;
     __shared__ __align__(16) uint32_t uni[UNI];  // slots + cnt + excl, later the pointer table
     __shared__ __align__(16) uint32_t wh[WAVES * SMAX];  // per-wave counts, later per-digit data
+    // EARLY: the tile's draws are published before it is staged, and the entries of
+    // the blocks drawn by earlier tiles are waited for after staging, which covers
+    // the time those tiles' publications take to become visible.  The per-digit
+    // data then needs its own arrays (staging still reads the wave offsets).
+    constexpr bool EARLY = !SEQ && !OOP;
+    __shared__ uint32_t pd_base[EARLY ? SMAX : 1], pd_nfw[EARLY ? SMAX : 1];
+    __shared__ uint2 pd_dt[EARLY ? SMAX : 1];
     __shared__ uint32_t tbo[SMAX];
     __shared__ uint32_t tphys[TBL];
     __shared__ uint32_t pool[OOP ? 1 : TBL];     // physical blocks of the tile's draws
-    __shared__ uint32_t fmask[E / 32], fpref[E / 32];
+    __shared__ uint32_t fmask[SEQ ? E / 32 : 1], fpref[SEQ ? E / 32 : 1];
+    __shared__ uint32_t fbo[SEQ ? 1 : SMAX];     // first draw of each digit (digit order)
     __shared__ uint32_t bphys[MAXBLK], blen[MAXBLK];
     __shared__ uint32_t tmp[3 * (NT / 64) + 2];
 
-    uint16_t* ls = (uint16_t*)uni;               // slot of each staged element
-    uint32_t* cnt = uni + E / 2;
-    uint32_t* excl = uni + E / 2 + SMAX;
+    uint16_t* ls = (uint16_t*)uni;               // slot of each staged element (SEQ)
+    uint32_t* cnt = uni + LSW;
+    uint32_t* excl = uni + LSW + SMAX;
 
     const uint32_t wlog = a.ring_log2;
     const uint64_t wmask = (1ull << wlog) - 1;
@@ -268,6 +302,9 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
         }
     };
     uint32_t first_tile = blockIdx.x;
+#ifdef RS_TIMELINE
+    const uint64_t t_entry = __builtin_amdgcn_s_memrealtime();
+#endif
     __shared__ uint32_t claimed;  // the tile claimed next (claimed forms)
     if constexpr (DYN != kPersistent) {
         if (tid == 0) claimed = add_agent(a.tile_ctr, 1u);
@@ -283,6 +320,11 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
     if constexpr (PF) load_tile(first_tile);
 
     for (uint32_t tile = first_tile, next; tile < ntiles; tile = next) {
+#ifdef RS_TIMELINE
+    if (tile == first_tile && tid == 0 && a.tl)
+        a.tl[(uint64_t)tile * kTlStamps + 15] = t_entry;
+#endif
+    RS_STAMP(0);
     // without PF the tile's loads are issued here; its block info is in LDS
     if constexpr (!PF) load_tile(tile);
     K key[ITEMS];
@@ -381,6 +423,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    RS_STAMP(1);
 
     // ---- per-digit tile counts (published at once) and wave offsets ------------------
     const uint32_t st0 = tile & ~(mst - 1);  // first tile of this tile's super-tile
@@ -439,9 +482,12 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
         }
     }
     __syncthreads();
+    RS_STAMP(2);
 
     // ---- stage in (digit, slot) order ------------------------------------------------
     // (with SPLIT, rk[j] keeps the staged position for the payload pass)
+    auto stage_tile = [&]() {
+    RS_STAMP(13);
     auto stage_items = [&](auto full) {
 #pragma unroll
         for (int j = 0; j < ITEMS; j++) {
@@ -450,7 +496,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                 const uint32_t p = wh[wave * SMAX + d] + (rk[j] >> 12);
                 lk[p] = key[j];
                 if constexpr (VB != 0 && !SPLIT) lv[p] = val[j];
-                ls[p] = (uint16_t)(wave * SEG + j * 64 + lane);
+                if constexpr (SEQ) ls[p] = (uint16_t)(wave * SEG + j * 64 + lane);
                 if constexpr (SPLIT) rk[j] = p;
             }
         }
@@ -459,12 +505,16 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
     else stage_items(std::false_type{});
     block_info_store(nx_phys, nx_len);
     __syncthreads();
+    RS_STAMP(3);
     // registers are free again: issue the next tile's loads
     if constexpr (PF) load_tile(next);
+    };
+    if constexpr (!EARLY) stage_tile();
 
-    uint32_t* base = wh;                  // per-digit data reusing the wave counts
-    uint32_t* nfw = wh + SMAX;
-    uint2* dt = (uint2*)(wh + 2 * SMAX);  // (rank offset, table offset) per digit
+    // per-digit data (reusing the wave counts once the tile is staged)
+    uint32_t* base = EARLY ? pd_base : wh;
+    uint32_t* nfw = EARLY ? pd_nfw : wh + SMAX;
+    uint2* dt = EARLY ? pd_dt : (uint2*)(wh + 2 * SMAX);  // (rank offset, table offset)
 
     // ---- look back over the super-tile -----------------------------------------------
     for (uint32_t d = tid; d < sigma; d += NT) {
@@ -504,6 +554,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
         base[d] = sbase + acc;
     }
     __syncthreads();
+    RS_STAMP(4);
     if (tid == 0) st_agent(a.done + (tile & wmask), tile + 1);
 
     if constexpr (OOP) {
@@ -566,13 +617,18 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
             if (d == tid && c && q0 > 0 && L < a.npi) first = ld_agent(a.pi_new + L);
             nfw[d] = (nfill << 16) | nwrite;
             tbo[d] = nwrite;
+            if constexpr (!SEQ) fbo[d] = nfill;
             fsum += q0;
             nsum += nfill;
             wsum += nwrite;
         }
-        for (uint32_t i = tid; i < E / 32; i += NT) fmask[i] = 0;
+        if constexpr (SEQ)
+            for (uint32_t i = tid; i < E / 32; i += NT) fmask[i] = 0;
         // F: draws made by earlier tiles; nfills: draws of this tile; with one
-        // digit per thread, also the scan of the blocks each digit writes
+        // digit per thread, also the scans of the blocks each digit writes and
+        // (digit order) of the blocks it draws
+        const uint32_t myfill = nsum;
+        const uint32_t fincl = (!SEQ && SMAX <= NT) ? wave_incl_scan(myfill) : 0u;
         fsum = wave_sum(fsum);
         nsum = wave_sum(nsum);
         const uint32_t wincl = SMAX <= NT ? wave_incl_scan(wsum) : 0u;
@@ -582,19 +638,25 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
         }
         if (SMAX <= NT && lane == 63) tmp[2 * (NT / 64) + wave] = wincl;
         __syncthreads();
-        uint32_t F = 0, nfills = 0, wbefore = 0, nent = 0;
+        uint32_t F = 0, nfills = 0, wbefore = 0, nent = 0, fbefore = 0;
 #pragma unroll
         for (int w = 0; w < NT / 64; w++) {
             F += tmp[w];
-            nfills += tmp[NT / 64 + w];
+            const uint32_t tf = tmp[NT / 64 + w];
+            nfills += tf;
+            fbefore += (uint32_t)w < wave ? tf : 0u;
             if constexpr (SMAX <= NT) {
                 const uint32_t t = tmp[2 * (NT / 64) + w];
                 wbefore += (uint32_t)w < wave ? t : 0u;
                 nent += t;
             }
         }
+        RS_STAMP(10);
         if constexpr (SMAX <= NT) {
-            if (tid < sigma) tbo[tid] = wbefore + wincl - wsum;
+            if (tid < sigma) {
+                tbo[tid] = wbefore + wincl - wsum;
+                if constexpr (!SEQ) fbo[tid] = fbefore + fincl - myfill;
+            }
         }
         // request the pool entries of the draws, and the done words of the
         // earlier tiles whose input blocks they are
@@ -610,16 +672,19 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
             if (olo + tid < ohi) dv = ld_agent(a.done + ((olo + tid) & wmask));
         }
         if constexpr (SMAX > NT) {
-            __syncthreads();  // tmp is reused by the scan
+            __syncthreads();  // tmp is reused by the scans
             nent = block_excl_scan<NT>(tbo, sigma, tmp);
+            if constexpr (!SEQ) block_excl_scan<NT>(fbo, sigma, tmp);
         }
         // mark the slots whose element fills a block
-        for (uint32_t d = tid; d < sigma; d += NT) {
-            const uint32_t nfill = nfw[d] >> 16, bs = base[d], q0 = bs >> log2b;
-            for (uint32_t i = 1; i <= nfill; i++) {
-                const uint32_t lr = ((q0 + i) << log2b) - 1 - bs;
-                const uint32_t s = ls[excl[d] + lr];
-                atomicOr(&fmask[s >> 5], 1u << (s & 31));
+        if constexpr (SEQ) {
+            for (uint32_t d = tid; d < sigma; d += NT) {
+                const uint32_t nfill = nfw[d] >> 16, bs = base[d], q0 = bs >> log2b;
+                for (uint32_t i = 1; i <= nfill; i++) {
+                    const uint32_t lr = ((q0 + i) << log2b) - 1 - bs;
+                    const uint32_t s = ls[excl[d] + lr];
+                    atomicOr(&fmask[s >> 5], 1u << (s & 31));
+                }
             }
         }
         // The drawn blocks are input blocks sigma + F .. sigma + F + nfills - 1.  Those
@@ -637,24 +702,32 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                 v = ld_agent(w);
             }
         }
-        __syncthreads();
-        for (uint32_t i = tid; i < E / 32; i += NT) fpref[i] = __popc(fmask[i]);
+        if constexpr (SEQ) {
+            __syncthreads();
+            for (uint32_t i = tid; i < E / 32; i += NT) fpref[i] = __popc(fmask[i]);
+        }
         if (tid < nfills) pool[tid] = pv;
         for (uint32_t i = tid + NT; i < nfills; i += NT) {  // more draws than threads: rare
             const uint32_t h = sigma + F + i;
             pool[i] = h < a.npi ? a.pi_old[h] : a.npi;
         }
         __syncthreads();
-        block_excl_scan<NT>(fpref, E / 32, tmp);
+        RS_STAMP(11);
+        if constexpr (SEQ) block_excl_scan<NT>(fpref, E / 32, tmp);
         // publish the tile's draws for every digit
         for (uint32_t d = tid; d < sigma; d += NT) {
             const uint32_t bs = base[d], q0 = bs >> log2b;
             const uint32_t nfill = nfw[d] >> 16, nwrite = nfw[d] & 0xFFFFu, t0 = tbo[d];
             const uint32_t Sd = a.S[d];
             for (uint32_t i = 1; i <= nfill; i++) {
-                const uint32_t lr = ((q0 + i) << log2b) - 1 - bs;
-                const uint32_t s = ls[excl[d] + lr];
-                const uint32_t r = fpref[s >> 5] + __popc(fmask[s >> 5] & ((1u << (s & 31)) - 1u));
+                uint32_t r;  // the draw's rank among the tile's draws
+                if constexpr (SEQ) {
+                    const uint32_t lr = ((q0 + i) << log2b) - 1 - bs;
+                    const uint32_t s = ls[excl[d] + lr];
+                    r = fpref[s >> 5] + __popc(fmask[s >> 5] & ((1u << (s & 31)) - 1u));
+                } else {
+                    r = fbo[d] + i - 1;
+                }
                 const uint32_t L = Sd + q0 + i;
                 uint32_t phys = r < nfills ? pool[r] : a.npi;
                 if (phys < a.npi && L < a.npi) {
@@ -666,6 +739,8 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                 if (i < nwrite) tphys[t0 + i] = phys;
             }
         }
+        RS_STAMP(12);
+        if constexpr (EARLY) stage_tile();
         // the block of each digit's first elements
         for (uint32_t d = tid; d < sigma; d += NT) {
             const uint32_t bs = base[d], c = cnt[d], q0 = bs >> log2b;
@@ -689,6 +764,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
             dt[d] = make_uint2(bs - excl[d], tbo[d] - q0);
         }
         __syncthreads();
+        RS_STAMP(5);
         for (uint32_t e = tid; e < nent; e += NT) {
             if (tphys[e] >= a.npi) {  // never for a consistent state: send the writes to T
                 raise_error(a.err, kErrBounds);
@@ -706,6 +782,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                     ptab[2 * e + 1] = (uint64_t)(uintptr_t)blockat(a.Av, a.Tv, j, two_sigma, log2b);
             }
             __syncthreads();
+            RS_STAMP(6);
             // ---- scatter ------------------------------------------------------------
             if constexpr (SPLIT) {
                 // keys first, remembering (table entry, offset) of each position;
@@ -732,6 +809,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                 if (tfull) scatter_keys(std::true_type{});
                 else scatter_keys(std::false_type{});
                 __syncthreads();  // every staged key was read
+                RS_STAMP(7);
                 if (wfull) {
 #pragma unroll
                     for (int j = 0; j < ITEMS; j++) lv[rk[j]] = val[j];
@@ -741,6 +819,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                         if (rk[j] != ~0u) lv[rk[j]] = val[j];
                 }
                 __syncthreads();
+                RS_STAMP(8);
                 auto scatter_vals = [&](auto full) {
 #pragma unroll
                     for (int i = 0; i < ITEMS; i++) {
@@ -753,6 +832,8 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                 };
                 if (tfull) scatter_vals(std::true_type{});
                 else scatter_vals(std::false_type{});
+                __builtin_amdgcn_s_waitcnt(0);
+                RS_STAMP(9);
             } else {
                 for (uint32_t p = tid; p < total; p += NT) {
                     const K k = lk[p];

@@ -27,6 +27,10 @@ using namespace rs;
 namespace {
 
 thread_local hipError_t g_last_hip = hipSuccess;
+#ifdef RS_TIMELINE
+uint64_t* g_tl = nullptr;  // stamps of the Radsort round kernel (timeline builds)
+uint64_t g_tl_tiles = 0;
+#endif
 radsort_stats g_stats{};
 
 #define RS_HIP(call)                                 \
@@ -67,7 +71,9 @@ int ilog2(uint64_t x)
 //     out (SPLIT).  Measured at 2^28 uint32 + uint32, b = 2048: Radsort round
 //     1.59 ms against 2.07 ms for shape 0, with one workgroup per tile;
 //   shapes 2-4 (tiles of 4096 slots, two to three workgroups per CU) measured
-//     slower (2.05-2.21 ms) and are kept for measurement only.
+//     slower (2.05-2.21 ms), shapes 5-6 (16 waves of 8 slots) spill registers;
+//     they are kept for measurement only (RS_ROUND_CFG selects a shape at build
+//     time, RS_RADSORT_FORM the launch form of the Radsort round).
 // The out-of-place round keeps shape 0 (1.50 ms, against 2.36 ms with shape 1).
 #ifndef RS_ROUND_CFG
 #define RS_ROUND_CFG 1
@@ -76,14 +82,15 @@ template <int KB, int VB, bool WIDE, bool OOP = false> struct TileCfg {
     static constexpr int C = (WIDE || OOP) ? 0 : RS_ROUND_CFG;
     static constexpr bool BIG = KB + VB >= 12;
     static constexpr bool NARROW = KB == 4 && VB <= 4;  // 8 bytes or less per record
-    static constexpr int WAVES = WIDE ? 4 : (C == 3 ? 4 : 8);
+    static constexpr int WAVES = WIDE ? 4 : (C == 3 ? 4 : C >= 5 ? 16 : 8);
     static constexpr int ITEMS = C == 0 ? (BIG ? 8 : 16)
                                : C == 1 ? (NARROW ? 16 : 8)
                                : C == 3 ? (BIG ? 8 : 16)
+                               : C >= 5 ? 8
                                         : 8;
     static constexpr bool PF = C == 0 || C == 4;
     static constexpr bool SPLIT = C != 0;
-    static constexpr int OCC = C == 0 ? 1 : C == 2 ? 6 : 4;
+    static constexpr int OCC = C == 0 ? 1 : C == 2 ? 6 : C == 5 ? 8 : C == 6 ? 6 : 4;
     using Shape = RoundShape<WAVES, ITEMS, PF, SPLIT, OCC>;
     static constexpr int E = 64 * WAVES * ITEMS;
 };
@@ -310,6 +317,7 @@ struct radsort_state {
     bool truncated = false;
     bool is_setup = false;
     bool dynamic = false;      // launch forms that need no co-residency (shared GPU)
+    bool seq_draws = false;    // draws in the sequential pool order (RADSORT_F_SEQ_DRAWS)
 
     uint32_t* u32(uint64_t off) const { return (uint32_t*)(ws + off); }
     uint32_t* pi(int which) const { return u32(which ? L.pi1 : L.pi0); }
@@ -419,11 +427,16 @@ int launch_dynamic(const void* kern, uint32_t tiles, uint32_t threads, Args& a, 
     return RADSORT_OK;
 }
 
+// seq: draws in the sequential pool order (pi as in the sequential algorithm);
+// otherwise in (digit, block) order within a tile.  Digits of more than 8 bits
+// always draw in the sequential order.  The out-of-place round draws nothing.
 template <int KB, int VB, bool OOP>
-int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = false)
+int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = false,
+                   bool seq = true)
 {
     using N = TileCfg<KB, VB, false, OOP>;
     using Wd = TileCfg<KB, VB, true, OOP>;
+    using NS = typename N::Shape;
     const uint32_t tiles = OOP ? (uint32_t)((g.n + g.oop_E - 1) / g.oop_E) : g.tiles;
     if (tiles == 0) return RADSORT_OK;
     // shapes without register prefetch take a workgroup per tile (the persistent
@@ -432,31 +445,36 @@ int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = 
     if (dyn) {
         // measured alone: one workgroup per tile for the Radsort round, the claim
         // loop for the out-of-place round
-        constexpr int M = OOP ? kClaimLoop : kPerTile;
-        if (g.bits == 8)
-            return launch_dynamic(
-                (const void*)&k_round<KB, VB, OOP, 8, 256, typename N::Shape, M>, tiles,
-                64 * N::WAVES, a, s, OOP);
-        if (g.bits < 8)
-            return launch_dynamic(
-                (const void*)&k_round<KB, VB, OOP, 0, 256, typename N::Shape, M>, tiles,
-                64 * N::WAVES, a, s, OOP);
+#ifndef RS_RADSORT_FORM
+#define RS_RADSORT_FORM kPerTile
+#endif
+        constexpr int M = OOP ? kClaimLoop : RS_RADSORT_FORM;
+        const uint32_t nt = 64 * N::WAVES;
+        const void* kern;
+        if (OOP || !seq)
+            kern = g.bits == 8 ? (const void*)&k_round<KB, VB, OOP, 8, 256, NS, M, false>
+                               : (const void*)&k_round<KB, VB, OOP, 0, 256, NS, M, false>;
+        else
+            kern = g.bits == 8 ? (const void*)&k_round<KB, VB, OOP, 8, 256, NS, M, true>
+                               : (const void*)&k_round<KB, VB, OOP, 0, 256, NS, M, true>;
+        if (g.bits <= 8) return launch_dynamic(kern, tiles, nt, a, s, OOP);
         return launch_dynamic(
-            (const void*)&k_round<KB, VB, OOP, 0, 2048, typename Wd::Shape, M>, tiles,
+            (const void*)&k_round<KB, VB, OOP, 0, 2048, typename Wd::Shape, M, !OOP>, tiles,
             64 * Wd::WAVES, a, s, OOP);
     }
     if constexpr (N::PF) {
-        if (g.bits == 8)
-            return launch_persistent(
-                (const void*)&k_round<KB, VB, OOP, 8, 256, typename N::Shape>, tiles,
-                64 * N::WAVES, a, s);
-        if (g.bits < 8)
-            return launch_persistent(
-                (const void*)&k_round<KB, VB, OOP, 0, 256, typename N::Shape>, tiles,
-                64 * N::WAVES, a, s);
+        const void* kern;
+        if (OOP || !seq)
+            kern = g.bits == 8 ? (const void*)&k_round<KB, VB, OOP, 8, 256, NS, kPersistent, false>
+                               : (const void*)&k_round<KB, VB, OOP, 0, 256, NS, kPersistent, false>;
+        else
+            kern = g.bits == 8 ? (const void*)&k_round<KB, VB, OOP, 8, 256, NS, kPersistent, true>
+                               : (const void*)&k_round<KB, VB, OOP, 0, 256, NS, kPersistent, true>;
+        if (g.bits <= 8) return launch_persistent(kern, tiles, 64 * N::WAVES, a, s);
     }
-    return launch_persistent((const void*)&k_round<KB, VB, OOP, 0, 2048, typename Wd::Shape>,
-                             tiles, 64 * Wd::WAVES, a, s);
+    return launch_persistent(
+        (const void*)&k_round<KB, VB, OOP, 0, 2048, typename Wd::Shape, kPersistent, !OOP>, tiles,
+        64 * Wd::WAVES, a, s);
 }
 
 template <int KB, int VB> struct Ops {
@@ -555,6 +573,9 @@ template <int KB, int VB> struct Ops {
         a.npi = g.npi;
         a.ring_log2 = g.ring_log2;
         a.st_log2 = g.st_log2;
+#ifdef RS_TIMELINE
+        a.tl = g.tiles <= g_tl_tiles ? g_tl : nullptr;
+#endif
         uint32_t* stcnt = (uint32_t*)(st->ws + st->L.stcnt);
         a.stbase = stcnt;
         // the ring is clear: setup or the previous round's fixup cleared it
@@ -563,7 +584,7 @@ template <int KB, int VB> struct Ops {
                                        st->u32(st->L.csum), a.err, a.tile_ctr + 1, r,
                                        st->plan(), s);
         g_timer.mark(kRoundBegin, r, s);
-        int rc = launch_round_t<KB, VB, false>(g, a, s, st->dynamic);
+        int rc = launch_round_t<KB, VB, false>(g, a, s, st->dynamic, st->seq_draws);
         if (rc) return rc;
         g_timer.mark(kRoundEnd, r, s);
         uint32_t grid = (uint32_t)std::min<uint64_t>((g.npi + 255) / 256, 4096);
@@ -977,6 +998,7 @@ int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_
     st->keys = keys;
     st->vals = payload;
     st->count = n;
+    st->seq_draws = opts && (opts->flags & RADSORT_F_SEQ_DRAWS);
     if (opts && opts->workspace) {
         if (opts->workspace_bytes < st->L.total) {
             delete st;
@@ -1395,3 +1417,15 @@ int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
 }
 
 }  // extern "C"
+
+#ifdef RS_TIMELINE
+// Timeline builds only (not part of include/radsort.h): later Radsort rounds write
+// kTlStamps real-time stamps per tile into buf (device memory of tiles * kTlStamps
+// words), each round over the previous one.
+extern "C" int radsort_timeline_buffer(void* buf, uint64_t tiles)
+{
+    g_tl = (uint64_t*)buf;
+    g_tl_tiles = buf ? tiles : 0;
+    return RADSORT_OK;
+}
+#endif

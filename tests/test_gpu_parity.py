@@ -1,10 +1,14 @@
 """GPU parity: the HIP path against the sequential oracle, through the C ABI.
 
-Every comparison is exact.  Radsort's integer state is deterministic: the GPU
-draws blocks from the pool in the same order as the sequential algorithm, so
-pi, P and f after setup and after every round must equal the oracle's bit for
-bit, and so must the permuted representation read in logical order and the
-final arrays.
+Every comparison is exact.  Radsort's integer state is deterministic.  With
+RADSORT_F_SEQ_DRAWS the GPU draws blocks from the pool in the same order as the
+sequential algorithm, so pi, P and f after setup and after every round must
+equal the oracle's bit for bit.  Without it (the default) a tile draws the same
+pool entries in (digit, block) order: P, f, the permuted representation read in
+logical order and the final arrays must still equal the oracle's, pi must be a
+permutation, and the sets of physical blocks in the head start, the allocated
+range and the unallocated tail must equal the oracle's (pi itself is not unique
+across valid draw orders).
 """
 import numpy as np
 import pytest
@@ -78,25 +82,48 @@ ROUND_CASES = [
 ]
 
 
+def check_pi(pi, prev, opi, i_out, sigma, exact, r):
+    """pi after round r: equal to the oracle's (sequential draws).  Otherwise it
+    must follow from the GPU's own pi before the round (prev) as Alg. 6 builds it
+    from any valid draw order: the round used the pool entries prev[0 .. i_out)
+    (i_out: the oracle's count of blocks taken), which now form the allocated
+    range sigma .. f-1 in some order; the next head start is prev[i_out ..
+    i_out + sigma) and the tail prev[i_out + sigma ..], both in order."""
+    pi = pi.astype(np.uint64)
+    if exact:
+        assert np.array_equal(pi, opi), f"pi differs after round {r}"
+        return
+    prev = prev.astype(np.uint64)
+    f = i_out + sigma
+    assert np.array_equal(pi[:sigma], prev[i_out:f]), f"head start after round {r}"
+    assert np.array_equal(np.sort(pi[sigma:f]), np.sort(prev[:i_out])), f"allocated, round {r}"
+    assert np.array_equal(pi[f:], prev[f:]), f"tail after round {r}"
+
+
+@pytest.mark.parametrize("seq", [True, False], ids=["seqdraws", "tiledraws"])
 @pytest.mark.parametrize("case", ROUND_CASES, ids=lambda c: "-".join(map(str, c)))
-def test_rounds_match_oracle(case):
+def test_rounds_match_oracle(case, seq):
     dist, n, kb, vb, bits, b = case
-    say(f"rounds {case}")
+    say(f"rounds {case} seq_draws={seq}")
     keys, vals = inputs(dist, n, kb, vb)
     sigma, nt = oracle.digit_params(kb, bits)
     dk = to_dev(keys)
     dv = to_dev(vals) if vb else None
-    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b)
+    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b, seq_draws=seq)
     R = oracle.Radsort(keys, vals, sigma, nt, b)
     st.setup()
     R.setup()
+    # digits of more than 8 bits always draw in the sequential order
+    exact = seq or bits > 8
+    prev = None
     for r in range(-1, nt):
         if r >= 0:
             st.round()
             R.round(nt - 1 - r)
         pi, pidx, plen, f = st.read()
         assert f == R.f, (r, f, R.f)
-        assert np.array_equal(pi.astype(np.uint64), R.pi()), f"pi differs after round {r}"
+        check_pi(pi, prev, R.pi(), R.i_out, sigma, exact or r < 0, r)
+        prev = pi
         oidx, olen = R.P()
         assert np.array_equal(pidx.astype(np.uint64), oidx), f"P idx differs after round {r}"
         assert np.array_equal(plen.astype(np.uint64), olen), f"P len differs after round {r}"
@@ -233,14 +260,17 @@ def test_ring_wraps_within_a_round():
 @pytest.mark.parametrize("b", [2048, 1024])
 def test_large_uniform_u32_matches_oracle(b):
     """n = 2^28 uint32 + index: the benchmark's input, compared element by element
-    with the oracle's result; the out-of-place baseline on the same input too."""
+    with the oracle's result (b = 2048 with the tile draw order the benchmark runs,
+    b = 1024 with the sequential one); the out-of-place baseline on the same input
+    too."""
     n = 1 << 28
     say(f"2^28 uint32 b={b}")
     keys = workloads.uniform(workloads.SEED_LARGE, n, 4)
     vals = np.arange(n, dtype=np.uint32)
     ok, ov = oracle.radsort(keys, vals, 256, 4, b)
     dk, dv = to_dev(keys), to_dev(vals)
-    radsort.sort_(dk, dv, block_elems=b, check=True)
+    # b = 1024 also covers the sequential draw order at full size
+    radsort.sort_(dk, dv, block_elems=b, check=True, seq_draws=(b == 1024))
     assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
     assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov)
     if b == 2048:

@@ -2,7 +2,8 @@
 (Alg. 8) between rounds, the block table of the permuted representation, keys
 rewritten in place through it, and a new sort of the same state.
 
-The oracle runs the same steps (truncate_count, set_logical, more rounds).  After
+The oracle runs the same steps (truncate_count, set_logical, more rounds), and the
+GPU draws blocks in the sequential order (RADSORT_F_SEQ_DRAWS).  After
 every step pi, P and f must equal the oracle's bit for bit, and so must the
 dataset read in logical order and, after finalize, the front of the arrays.
 """
@@ -80,7 +81,7 @@ def test_truncate_between_rounds_matches_oracle(case, at):
         vals = np.arange(n, dtype=NP[vb]) if vb else None
         dk = to_dev(keys)
         dv = to_dev(vals) if vb else None
-        st = radsort.State(dk, dv, digit_bits=bits, block_elems=b)
+        st = radsort.State(dk, dv, digit_bits=bits, block_elems=b, seq_draws=True)
         R = oracle.Radsort(keys, vals, sigma, nt, b)
         st.setup()
         R.setup()
@@ -146,7 +147,8 @@ def test_sort_again_without_finalize(kb, vb, b):
     vals = np.arange(n, dtype=NP[vb])
     dk, dv = to_dev(keys), to_dev(vals)
     ws = torch.empty(radsort.workspace_bytes(n, kb, vb, bits, b), dtype=torch.uint8, device=DEV)
-    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b, workspace=ws)
+    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b, workspace=ws,
+                       seq_draws=True)
     R = oracle.Radsort(keys, vals, sigma, nt, b)
     st.setup()
     R.setup()
@@ -186,7 +188,8 @@ def test_block_table_matches_oracle_state():
     sigma, nt = oracle.digit_params(kb, bits)
     keys = workloads.make("zipf", 5, n, kb)
     vals = np.arange(n, dtype=np.uint32)
-    st = radsort.State(to_dev(keys), to_dev(vals), digit_bits=bits, block_elems=b)
+    st = radsort.State(to_dev(keys), to_dev(vals), digit_bits=bits, block_elems=b,
+                       seq_draws=True)
     R = oracle.Radsort(keys, vals, sigma, nt, b)
     st.setup()
     R.setup()
@@ -218,7 +221,7 @@ def test_truncate_edges():
     keys = workloads.make("uniform", 9, n, kb)
     vals = np.arange(n, dtype=np.uint32)
     dk, dv = to_dev(keys), to_dev(vals)
-    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b)
+    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b, seq_draws=True)
     R = oracle.Radsort(keys, vals, sigma, nt, b)
     st.setup()
     R.setup()
@@ -258,7 +261,7 @@ def test_truncate_at_scale(kb, b):
     keys = workloads.make("uniform", 123, n, kb)
     vals = np.arange(n, dtype=np.uint32)
     dk, dv = to_dev(keys), to_dev(vals)
-    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b)
+    st = radsort.State(dk, dv, digit_bits=bits, block_elems=b, seq_draws=True)
     R = oracle.Radsort(keys, vals, sigma, nt, b)
     st.setup()
     R.setup()
