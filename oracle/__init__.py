@@ -80,6 +80,9 @@ def _bind(lib):
         "orc_truncate_count": (ctypes.c_int, [vp, u64]),
         "orc_set_logical": (None, [vp, _U64P, _U64P]),
         "orc_n": (u64, [vp]),
+        "orc_test_set_pi": (None, [vp, u64, u64]),
+        "orc_test_set_P": (None, [vp, u64, u64, u64]),
+        "orc_test_set_f": (None, [vp, u64]),
         "orc_oop_lsd": (ctypes.c_int, [_U64P, _U64P, u64, u64, u64, u64]),
         "orc_histograms": (None, [_U64P, u64, u64, u64, _U64P]),
         "orc_extra_bytes": (u64, [u64, u64, u64, u64, u64, u64]),
@@ -177,6 +180,16 @@ class Radsort:
         if len(k) != self.n or (v is not None and len(v) != self.n):
             raise ValueError("set_logical needs exactly n elements")
         self.lib.orc_set_logical(self._st, _p(k), _p(v))
+
+    # test hooks: plant a broken state (for the pins of the invariant checker)
+    def plant_pi(self, i, v):
+        self.lib.orc_test_set_pi(self._st, i, v)
+
+    def plant_P(self, k, idx, length):
+        self.lib.orc_test_set_P(self._st, k, idx, length)
+
+    def plant_f(self, f):
+        self.lib.orc_test_set_f(self._st, f)
 
     # inspection
     @property

@@ -44,9 +44,10 @@
  *       block of the tail that sits in the A block right after the homes is first
  *       moved to a free block of T (the tail copies write into that A block).
  *
- * Lemma 1 is asserted in its tight form: when a new output block is drawn during
- * the scan, i_out < i_in, or i_out == i_in and the element just written was the
- * last element of input block i_in (that block has then been read completely).
+ * Lemma 1 is asserted in its tight form: when a bucket takes a new block during
+ * the scan, the pool entry it takes lies before the input block being read, or is
+ * that block when the element just written was its last one (the block has then
+ * been read completely).
  */
 #include "radsort_oracle.h"
 
@@ -61,12 +62,16 @@ struct orc_state {
     uint64_t f;         /* fill level */
     uint64_t *pi;       /* logical -> physical block, n_pi entries */
     uint64_t *Pi, *Pl;  /* partial blocks: logical index and length, sigma entries */
-    /* round temporaries (Sec. 2.3) */
-    orc_elem **Bnext, **Bend;
-    uint64_t *C, *S;
-    uint32_t *U;
+    /* round temporaries (Sec. 2.3), kept in this oracle's own form: the blocks a
+     * round takes are numbered by their place in the pool pi[0], pi[1], ...; each
+     * bucket has a cursor (the pool entry of the block it is filling and how many
+     * elements that block holds); owner[h] is the bucket that took pool entry h;
+     * blocks_of[c] counts the blocks bucket c took; taken counts the pool entries
+     * handed out so far. */
+    uint64_t *cur_entry, *cur_fill, *blocks_of, *start;
+    uint32_t *owner;
     uint64_t *pi2;
-    uint64_t i_out;
+    uint64_t taken;
     /* finalize temporaries (Sec. 2.4) */
     uint64_t *pinv;
     /* instrumentation */
@@ -123,15 +128,15 @@ orc_state *orc_create(uint64_t n, uint64_t sigma, uint64_t nt, uint64_t b)
     st->pi = calloc(st->npi, sizeof(uint64_t));
     st->pi2 = calloc(st->npi, sizeof(uint64_t));
     st->pinv = calloc(st->npi, sizeof(uint64_t));
-    st->U = calloc(st->npi, sizeof(uint32_t));
+    st->owner = calloc(st->npi, sizeof(uint32_t));
     st->Pi = calloc(sigma, sizeof(uint64_t));
     st->Pl = calloc(sigma, sizeof(uint64_t));
-    st->C = calloc(sigma, sizeof(uint64_t));
-    st->S = calloc(sigma, sizeof(uint64_t));
-    st->Bnext = calloc(sigma, sizeof(orc_elem *));
-    st->Bend = calloc(sigma, sizeof(orc_elem *));
-    if (!st->A || !st->T || !st->pi || !st->pi2 || !st->pinv || !st->U || !st->Pi ||
-        !st->Pl || !st->C || !st->S || !st->Bnext || !st->Bend) {
+    st->cur_entry = calloc(sigma, sizeof(uint64_t));
+    st->cur_fill = calloc(sigma, sizeof(uint64_t));
+    st->blocks_of = calloc(sigma, sizeof(uint64_t));
+    st->start = calloc(sigma, sizeof(uint64_t));
+    if (!st->A || !st->T || !st->pi || !st->pi2 || !st->pinv || !st->owner || !st->Pi ||
+        !st->Pl || !st->cur_entry || !st->cur_fill || !st->blocks_of || !st->start) {
         orc_destroy(st);
         return NULL;
     }
@@ -142,8 +147,8 @@ void orc_destroy(orc_state *st)
 {
     if (!st) return;
     free(st->A); free(st->T); free(st->pi); free(st->pi2); free(st->pinv);
-    free(st->U); free(st->Pi); free(st->Pl); free(st->C); free(st->S);
-    free(st->Bnext); free(st->Bend);
+    free(st->owner); free(st->Pi); free(st->Pl); free(st->cur_entry); free(st->cur_fill);
+    free(st->blocks_of); free(st->start);
     free(st);
 }
 
@@ -195,73 +200,87 @@ static uint64_t size_of_next_block(const orc_state *st, uint64_t i, uint64_t *iP
     return st->b;
 }
 
-/* ---- newBucketBlock and sortPhase (Alg. 5) -------------------------------------- */
+/* ---- sortPhase with newBucketBlock (Alg. 5) --------------------------------------
+ *
+ * The pool is pi read in logical order: its first sigma entries are the head
+ * start, then come the input blocks sigma .. f-1, then the unallocated ones.  A
+ * bucket holds one open block at a time; when that block has received b elements
+ * the bucket takes the next pool entry (eager allocation, reading G5).  Lemma 1
+ * says the entry taken then is an input block the scan has already passed. */
 
-static void new_bucket_block(orc_state *st, uint64_t c)
+/* Hands bucket c the next pool entry as its open, empty block.  Returns 0 when
+ * the pool is exhausted (never for a correct state: Lemma 1); the scan then stops
+ * and the round's state is not usable. */
+static int give_block(orc_state *st, uint64_t c)
 {
-    if (st->i_out >= st->npi) { st->counters[ORC_C_POOL_OVERRUN]++; return; }
-    orc_elem *p = blockat(st, st->pi[st->i_out]);
-    st->Bnext[c] = p;
-    st->Bend[c] = p + st->b;
-    st->C[c]++;
-    st->U[st->i_out] = (uint32_t)c;
-    st->i_out++;
+    if (st->taken >= st->npi) { st->counters[ORC_C_POOL_OVERRUN]++; return 0; }
+    st->cur_entry[c] = st->taken;
+    st->cur_fill[c] = 0;
+    st->owner[st->taken] = (uint32_t)c;
+    st->blocks_of[c]++;
+    st->taken++;
+    return 1;
 }
 
 void orc_sort_phase(orc_state *st, uint64_t t)
 {
-    uint64_t sigma = st->sigma, iP = 0;
-    for (uint64_t c = 0; c < sigma; c++) st->C[c] = 0;
-    st->i_out = 0;
-    for (uint64_t c = 0; c < sigma; c++) new_bucket_block(st, c);
-    for (uint64_t i_in = sigma; i_in < st->f; i_in++) {
-        orc_elem *p_in = blockat(st, st->pi[i_in]);
-        uint64_t l = size_of_next_block(st, i_in, &iP);
-        for (uint64_t j = 0; j < l; j++) {
-            uint64_t c = orc_key(p_in[j].key, t, sigma, st->nt);
-            orc_elem *p_next = st->Bnext[c];
-            *p_next = p_in[j];
-            if (p_next + 1 == st->Bend[c]) {
-                /* Lemma 1, tight form */
-                if (st->i_out < i_in) {
-                    /* strict case of the lemma */
-                } else if (st->i_out == i_in && j + 1 == l) {
-                    st->counters[ORC_C_LEMMA1_EQUAL]++;
-                } else {
-                    st->counters[ORC_C_LEMMA1_VIOLATION]++;
-                }
-                new_bucket_block(st, c);
-            } else {
-                st->Bnext[c] = p_next + 1;
-            }
+    const uint64_t sigma = st->sigma, b = st->b;
+    st->taken = 0;
+    for (uint64_t c = 0; c < sigma; c++) st->blocks_of[c] = 0;
+    for (uint64_t c = 0; c < sigma; c++)    /* every bucket starts in its head-start block */
+        if (!give_block(st, c)) return;
+    uint64_t iP = 0;
+    for (uint64_t L = sigma; L < st->f; L++) {            /* input blocks in logical order */
+        const uint64_t len = size_of_next_block(st, L, &iP);
+        const orc_elem *in = blockat(st, st->pi[L]);
+        for (uint64_t j = 0; j < len; j++) {
+            const uint64_t c = orc_key(in[j].key, t, st->sigma, st->nt);
+            orc_elem *out = blockat(st, st->pi[st->cur_entry[c]]);
+            out[st->cur_fill[c]] = in[j];
+            st->cur_fill[c]++;
+            if (st->cur_fill[c] < b) continue;
+            /* the block is full: the bucket needs the next pool entry.  Lemma 1, tight
+             * form: that entry is a block the scan has left, or the current input
+             * block L when this element was its last one. */
+            if (st->taken == L && j + 1 == len) st->counters[ORC_C_LEMMA1_EQUAL]++;
+            else if (st->taken >= L) st->counters[ORC_C_LEMMA1_VIOLATION]++;
+            if (!give_block(st, c)) return;
         }
     }
 }
 
-/* ---- fixupPhase (Alg. 6) ------------------------------------------------------------ */
-
+/* ---- fixupPhase (Alg. 6) -------------------------------------------------------------
+ *
+ * The new logical order lists the buckets one after the other behind a fresh head
+ * start: bucket c's blocks, in the order it took them, go to logical indices
+ * start[c] .. start[c] + blocks_of[c] - 1 with start[c] = sigma + the blocks of
+ * the buckets before c.  Each bucket's last block is the one it is still
+ * filling, which becomes its partial block in P.  The next sigma pool entries
+ * after the taken ones become the head start; entries past them stay where they
+ * are.  Lemma 2 says at least sigma entries are left for that head start. */
 void orc_fixup_phase(orc_state *st)
 {
-    uint64_t sigma = st->sigma, npi = st->npi, i_out = st->i_out;
-    if (npi - i_out < sigma) {            /* Lemma 2 */
+    const uint64_t sigma = st->sigma, npi = st->npi, taken = st->taken;
+    if (npi < taken + sigma) {                           /* Lemma 2 */
         st->counters[ORC_C_LEMMA2_VIOLATION]++;
         return;
     }
-    st->S[0] = sigma;
-    for (uint64_t i = 1; i < sigma; i++) st->S[i] = st->S[i - 1] + st->C[i - 1];
-    for (uint64_t i = 0; i < sigma; i++) st->pi2[i] = st->pi[i_out + i];   /* head start */
-    for (uint64_t i = 0; i < i_out; i++) {
-        uint64_t c = st->U[i];
-        st->pi2[st->S[c]] = st->pi[i];
-        orc_elem *base = blockat(st, st->pi[i]);
-        if (st->Bend[c] == base + st->b) {                                  /* partial? */
-            st->Pi[c] = st->S[c];
-            st->Pl[c] = (uint64_t)(st->Bnext[c] - base);
-        }
-        st->S[c]++;
+    uint64_t next_free = sigma;
+    for (uint64_t c = 0; c < sigma; c++) {
+        st->start[c] = next_free;
+        next_free += st->blocks_of[c];
     }
-    for (uint64_t i = i_out + sigma; i < npi; i++) st->pi2[i] = st->pi[i]; /* the rest */
-    st->f = i_out + sigma;
+    for (uint64_t c = 0; c < sigma; c++) {               /* partial block of each bucket */
+        st->Pi[c] = st->start[c] + st->blocks_of[c] - 1;
+        st->Pl[c] = st->cur_fill[c];
+    }
+    for (uint64_t h = 0; h < taken; h++) {               /* blocks in bucket order */
+        const uint64_t c = st->owner[h];
+        st->pi2[st->start[c]++] = st->pi[h];
+    }
+    for (uint64_t k = 0; k < sigma; k++) st->pi2[k] = st->pi[taken + k];   /* head start */
+    for (uint64_t L = taken + sigma; L < npi; L++) st->pi2[L] = st->pi[L]; /* unallocated */
+    st->f = taken + sigma;
     uint64_t *tmp = st->pi;
     st->pi = st->pi2;
     st->pi2 = tmp;
@@ -302,6 +321,10 @@ void orc_finalize(orc_state *st)
             i_out = i_free;                         /* G3: the pair (i_out, j_out) */
         }
         uint64_t l = size_of_next_block(st, i_in, &iP);
+        if (k + l > st->n) {  /* the lengths add up to more than n: a broken state */
+            st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
+            return;
+        }
         memmove(st->A + k, blockat(st, j_in), l * sizeof(orc_elem));   /* pull */
         st->counters[ORC_C_FINALIZE_COPIES]++;
         k += l;
@@ -338,6 +361,10 @@ void orc_finalize(orc_state *st)
         if (j_in >= 2 * sigma && j_in - 2 * sigma <= nb)
             st->counters[ORC_C_FINALIZE_TAIL_OVERWRITTEN]++;
         uint64_t l = size_of_next_block(st, i_in, &iP);
+        if (k + l > st->n) {
+            st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
+            return;
+        }
         memmove(st->A + k, blockat(st, j_in), l * sizeof(orc_elem));
         st->counters[ORC_C_FINALIZE_COPIES]++;
         k += l;
@@ -407,6 +434,23 @@ void orc_set_logical(orc_state *st, const uint64_t *keys, const uint64_t *vals)
 
 uint64_t orc_n(const orc_state *st) { return st->n; }
 
+/* ---- test hooks: plant a broken state for the invariant checker's pins ------------ */
+
+void orc_test_set_pi(orc_state *st, uint64_t i, uint64_t v)
+{
+    if (i < st->npi) st->pi[i] = v;
+}
+
+void orc_test_set_P(orc_state *st, uint64_t k, uint64_t idx, uint64_t len)
+{
+    if (k < st->sigma) {
+        st->Pi[k] = idx;
+        st->Pl[k] = len;
+    }
+}
+
+void orc_test_set_f(orc_state *st, uint64_t f) { st->f = f; }
+
 /* ---- the driver (Alg. 2) ----------------------------------------------------------- */
 
 int orc_radsort(uint64_t *keys, uint64_t *vals, uint64_t n, uint64_t sigma, uint64_t nt,
@@ -417,10 +461,13 @@ int orc_radsort(uint64_t *keys, uint64_t *vals, uint64_t n, uint64_t sigma, uint
     orc_load(st, keys, vals);
     orc_setup(st);
     for (uint64_t t = nt; t-- > 0;) orc_round(st, t);
-    orc_finalize(st);
-    orc_store(st, keys, vals);
     int bad = 0;
     for (int c = ORC_C_FIRST_ERROR; c < ORC_NCOUNTERS; c++) bad |= st->counters[c] != 0;
+    if (!bad) {  /* a state whose rounds broke a lemma is not finalized */
+        orc_finalize(st);
+        for (int c = ORC_C_FIRST_ERROR; c < ORC_NCOUNTERS; c++) bad |= st->counters[c] != 0;
+    }
+    orc_store(st, keys, vals);
     orc_destroy(st);
     return bad ? -2 : 0;
 }
@@ -429,7 +476,7 @@ int orc_radsort(uint64_t *keys, uint64_t *vals, uint64_t n, uint64_t sigma, uint
 
 uint64_t orc_npi(const orc_state *st) { return st->npi; }
 uint64_t orc_f(const orc_state *st) { return st->f; }
-uint64_t orc_i_out(const orc_state *st) { return st->i_out; }
+uint64_t orc_i_out(const orc_state *st) { return st->taken; }
 
 void orc_get_pi(const orc_state *st, uint64_t *out)
 {
@@ -444,7 +491,7 @@ void orc_get_P(const orc_state *st, uint64_t *idx, uint64_t *len)
 
 void orc_get_C(const orc_state *st, uint64_t *out)
 {
-    memcpy(out, st->C, st->sigma * sizeof(uint64_t));
+    memcpy(out, st->blocks_of, st->sigma * sizeof(uint64_t));
 }
 
 void orc_get_counters(const orc_state *st, uint64_t *out)

@@ -53,6 +53,10 @@ int orc_truncate(orc_state *st, uint64_t i, int64_t j);
 int orc_truncate_count(orc_state *st, uint64_t count);
 void orc_set_logical(orc_state *st, const uint64_t *keys, const uint64_t *vals);
 uint64_t orc_n(const orc_state *st);
+/* test hooks: overwrite one entry of pi or P, or f, to plant a broken state */
+void orc_test_set_pi(orc_state *st, uint64_t i, uint64_t v);
+void orc_test_set_P(orc_state *st, uint64_t k, uint64_t idx, uint64_t len);
+void orc_test_set_f(orc_state *st, uint64_t f);
 
 int orc_oop_lsd(uint64_t *keys, uint64_t *vals, uint64_t n, uint64_t sigma, uint64_t nt,
                 uint64_t rounds);

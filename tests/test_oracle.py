@@ -292,3 +292,58 @@ def test_key_positions_by_hand():
     assert oracle.key(2 * 9 + 1 * 3 + 2, 0, 3, 3) == 2      # base-3 tuple (2, 1, 2)
     assert oracle.key(2 * 9 + 1 * 3 + 2, 1, 3, 3) == 1
     assert oracle.key(2 * 9 + 1 * 3 + 2, 2, 3, 3) == 2
+
+
+# ---------------------------------------------------------------- the invariant checker
+
+def _state_after_one_round(b=64, n=20000, lib=None):
+    keys = workloads.uniform(0xC0DE, n, 4)
+    R = oracle.Radsort(keys, np.arange(n), 256, 4, b, lib=lib)
+    R.setup()
+    R.round(3)
+    assert R.invariant() == 0
+    return R
+
+
+def _plant(R, case):
+    """Plants one broken clause of the data invariant (Sec. 2.2) into a valid state."""
+    sigma, npi, f = R.sigma, R.npi, R.f
+    pi = R.pi()
+    idx, ln = R.P()
+    if case == "pi_duplicate":            # clause 1: pi is a permutation
+        R.plant_pi(sigma + 1, int(pi[sigma + 2]))
+    elif case == "pi_out_of_range":
+        R.plant_pi(5, npi)
+    elif case == "P_not_ascending":       # clause 2: P ascending, partial lengths < b
+        R.plant_P(3, int(idx[4]), int(ln[4]))
+        R.plant_P(4, int(idx[3]), int(ln[3]))
+    elif case == "P_in_head_start":
+        R.plant_P(0, sigma - 1, int(ln[0]))
+    elif case == "partial_block_full":
+        k = int(np.flatnonzero(idx != f - 1)[0])
+        R.plant_P(k, int(idx[k]), R.b)
+    elif case == "last_block_not_partial":  # clause 3: block f-1 is partial
+        assert f + 1 <= npi
+        R.plant_f(f + 1)
+    elif case == "f_past_npi":            # clause 4: the allocated range ends inside n_pi
+        R.plant_P(sigma - 1, npi, 0)
+        R.plant_f(npi + 1)
+    elif case == "lengths_miss_n":        # the used lengths add up to n
+        k = int(np.flatnonzero(ln > 0)[0])
+        R.plant_P(k, int(idx[k]), int(ln[k]) - 1)
+    else:
+        raise ValueError(case)
+
+
+BROKEN = {"pi_duplicate": 1, "pi_out_of_range": 1, "P_not_ascending": 2, "P_in_head_start": 2,
+          "partial_block_full": 2, "last_block_not_partial": 3, "f_past_npi": 4,
+          "lengths_miss_n": 5}
+
+
+@pytest.mark.parametrize("case", sorted(BROKEN))
+def test_invariant_checker_names_the_broken_clause(case):
+    """A checker that always answers 'fine' (or checks the wrong clause) fails here:
+    each planted state breaks exactly one clause of the invariant of Sec. 2.2."""
+    R = _state_after_one_round()
+    _plant(R, case)
+    assert R.invariant() == BROKEN[case], case
