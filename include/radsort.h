@@ -297,6 +297,26 @@ int radsort_state_dims(const radsort_state* st, uint32_t* npi, uint32_t* sigma,
 /* Frees the state and the workspace it allocated (call after the stream is done). */
 int radsort_state_destroy(radsort_state* st);
 
+/* ---- for callers that cannot allocate ------------------------------------------
+ * For code under HIP graph capture, tight serving loops and harnesses that forbid
+ * device allocation: radsort_sort_pairs with its workspace taken from a static
+ * device array of the library, RADSORT_NOALLOC_SCRATCH_BYTES per GPU, held by every
+ * GPU the library runs on until the process ends.  The call allocates nothing, on
+ * the device or the host (it makes no hipMalloc, hipFree, event or state
+ * allocation).  Arguments as radsort_sort_pairs, with block_elems (b, 0 selects
+ * 1024) and flags (RADSORT_F_CHECK, RADSORT_F_SEQ_DRAWS; RADSORT_F_TIMING, which
+ * creates events, is rejected with RADSORT_E_INVALID) given directly.  A sort whose
+ * workspace (radsort_workspace_bytes) exceeds the static array returns
+ * RADSORT_E_NOMEM before anything is enqueued; for 8-bit digits and b = 2048 the
+ * array holds the workspace of up to about 2^28 uint32 key + uint32 payload pairs.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other threads) race and give undefined results; calls ordered on
+ * one stream are safe, each clearing what it needs. */
+#define RADSORT_NOALLOC_SCRATCH_BYTES (32ull << 20)
+int radsort_sort_pairs_noalloc(void* keys, void* payload, uint64_t n, int key_bytes,
+                               int payload_bytes, int digit_bits, uint32_t block_elems,
+                               uint32_t flags, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,9 @@ ABI = [
     "radsort_sort_segments", "radsort_segments_workspace_bytes",
     "radsort_state_blocks", "radsort_state_planes", "radsort_state_count",
     "radsort_state_truncate", "radsort_state_restart", "radsort_workspace_error",
+    "radsort_sort_pairs_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 32 << 20  # RADSORT_NOALLOC_SCRATCH_BYTES
 SEG_CLASSES = 32
 
 
@@ -81,6 +83,8 @@ def load(path: str | None = None):
     op = ctypes.POINTER(Opts)
     sig = {
         "radsort_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
+        "radsort_sort_pairs_noalloc": (i32, [vp, vp, u64, i32, i32, i32, ctypes.c_uint32,
+                                             ctypes.c_uint32, vp]),
         "radsort_sort": (i32, [vp, u64, i32, i32, vp]),
         "radsort_workspace_bytes": (u64, [u64, i32, i32, i32, op]),
         "radsort_oop_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
@@ -189,6 +193,22 @@ def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, works
             ctypes.c_void_p(keys.data_ptr()),
             ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
             keys.numel(), kb, vb, digit_bits, ctypes.byref(o), _stream(stream, keys.device))
+    _check(rc)
+    return keys, payload
+
+
+def sort_noalloc_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None,
+                  check=False, seq_draws=False):
+    """Radsort in place with the library's static scratch as workspace
+    (radsort_sort_pairs_noalloc): allocates nothing.  Calls overlapping on one GPU
+    share that scratch and race."""
+    kb, vb = _validate(keys, payload)
+    flags = (F_CHECK if check else 0) | (F_SEQ_DRAWS if seq_draws else 0)
+    with _device(keys):
+        rc = load().radsort_sort_pairs_noalloc(
+            ctypes.c_void_p(keys.data_ptr()),
+            ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
+            keys.numel(), kb, vb, digit_bits, block_elems, flags, _stream(stream, keys.device))
     _check(rc)
     return keys, payload
 

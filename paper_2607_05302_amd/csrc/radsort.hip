@@ -1418,6 +1418,87 @@ int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
 
 }  // extern "C"
 
+// ---- the allocation-free entry point ----------------------------------------------
+//
+// radsort_sort_pairs_noalloc sorts with a workspace that is a file-scope device
+// array, `scratch`, instead of a caller buffer or an allocation: each GPU the
+// library runs on holds RADSORT_NOALLOC_SCRATCH_BYTES of it from the time the code
+// object is loaded until the process ends.  In host code `scratch` names a host
+// stand-in, never the device memory: its device address is looked up once per
+// device (hipGetSymbolAddress, with that device current) and only that address is
+// passed to kernels.  Every call on one GPU shares the array; the kernels clear
+// what must start at zero (setup's fills), and calls that overlap on one GPU race.
+
+static __device__ __align__(256) uint8_t scratch[RADSORT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxScratchDevices];  // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device (looked up on first use).
+int scratch_address(void** out)
+{
+    int dev = 0;
+    RS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return RADSORT_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        RS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return RADSORT_E_DEVICE;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return RADSORT_OK;
+}
+
+}  // namespace
+
+int radsort_sort_pairs_noalloc(void* keys, void* payload, uint64_t n, int key_bytes,
+                               int payload_bytes, int digit_bits, uint32_t block_elems,
+                               uint32_t flags, void* stream)
+{
+    // timing records HIP events, which the library creates (allocates) on first use
+    if (flags & RADSORT_F_TIMING) return RADSORT_E_INVALID;
+    int rc = check_args(keys, payload, n, payload_bytes);
+    if (rc) return rc;
+    radsort_opts o{};
+    o.block_elems = block_elems;
+    o.flags = flags;
+    Geo g;
+    rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, &o);
+    if (rc) return rc;
+    if (n <= 1) return RADSORT_OK;
+    const Layout L = make_layout(g, false);
+    if (L.total > (uint64_t)RADSORT_NOALLOC_SCRATCH_BYTES) return RADSORT_E_NOMEM;
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    radsort_state st;  // on the stack: nothing is allocated, on the host either
+    st.g = g;
+    st.L = L;
+    st.ws = (uint8_t*)ws;
+    st.own_ws = false;
+    st.keys = keys;
+    st.vals = payload;
+    st.count = n;
+    st.seq_draws = flags & RADSORT_F_SEQ_DRAWS;
+    // the launch forms that query no occupancy (the query's cache allocates)
+    st.dynamic = true;
+    hipStream_t s = (hipStream_t)stream;
+    rc = radsort_state_setup(&st, s);
+    for (uint32_t r = 0; !rc && r < st.g.nt; r++) rc = radsort_state_round(&st, s);
+    if (!rc) rc = radsort_state_finalize(&st, s);
+    g_stats.timed = 0;
+    g_stats.workspace_bytes = L.total;
+    g_stats.input_bytes = n * (uint64_t)(key_bytes + payload_bytes);
+    g_stats.rounds = st.g.nt;
+    if (!rc && (flags & RADSORT_F_CHECK)) rc = read_err(&st, s, nullptr);
+    return rc;
+}
+
 #ifdef RS_TIMELINE
 // Timeline builds only (not part of include/radsort.h): later Radsort rounds write
 // kTlStamps real-time stamps per tile into buf (device memory of tiles * kTlStamps

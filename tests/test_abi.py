@@ -138,3 +138,22 @@ def test_strerror_texts():
 def test_binding_fails_loudly_without_library(tmp_path):
     with pytest.raises(RuntimeError):
         radsort.load(str(tmp_path / "missing.so"))
+
+
+def test_noalloc_refusals_need_no_device():
+    """radsort_sort_pairs_noalloc refuses a workspace past its static scratch, and
+    the timing flag, before touching the device."""
+    lib = radsort.load()
+    fake = ctypes.c_void_p(0x1000)
+    text = open(HEADER).read()
+    m = re.search(r"#define RADSORT_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == radsort.NOALLOC_SCRATCH_BYTES
+    n = 1 << 30
+    assert radsort.workspace_bytes(n, 4, 4, 8, 1024) > radsort.NOALLOC_SCRATCH_BYTES
+    assert lib.radsort_sort_pairs_noalloc(fake, fake, n, 4, 4, 8, 1024, 0, None) == \
+        radsort.E_NOMEM
+    assert lib.radsort_sort_pairs_noalloc(fake, fake, 1000, 4, 4, 8, 1024, radsort.F_TIMING,
+                                          None) == radsort.E_INVALID
+    assert lib.radsort_sort_pairs_noalloc(fake, fake, 1000, 3, 4, 8, 1024, 0, None) == \
+        radsort.E_INVALID
+    assert lib.radsort_sort_pairs_noalloc(None, None, 0, 4, 0, 8, 0, 0, None) == radsort.OK
