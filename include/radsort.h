@@ -297,6 +297,19 @@ int radsort_state_dims(const radsort_state* st, uint32_t* npi, uint32_t* sigma,
 /* Frees the state and the workspace it allocated (call after the stream is done). */
 int radsort_state_destroy(radsort_state* st);
 
+/* MSD-first split (Sec. 4.3, last paragraph): one Radsort round on the most
+ * significant digit, then finalize, which leaves the array grouped by that digit;
+ * then every group is sorted by the remaining digits as one batch of independent
+ * arrays (radsort_sort_segments).  The result equals radsort_sort_pairs'.
+ * Arguments as radsort_sort_pairs; opts->workspace must be NULL (the library
+ * allocates each phase's workspace and frees it: the peak is the larger of the
+ * round's workspace and the batch's, reported by radsort_last_stats), and the
+ * call waits for the stream once, between the two phases, to read the group
+ * sizes.  Errors as radsort_sort_pairs. */
+int radsort_msd_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
+                           int payload_bytes, int digit_bits, const radsort_opts* opts,
+                           void* stream);
+
 /* ---- for callers that cannot allocate ------------------------------------------
  * For code under HIP graph capture, tight serving loops and harnesses that forbid
  * device allocation: radsort_sort_pairs with its workspace taken from a static

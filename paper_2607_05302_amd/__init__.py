@@ -34,7 +34,7 @@ ABI = [
     "radsort_sort_segments", "radsort_segments_workspace_bytes",
     "radsort_state_blocks", "radsort_state_planes", "radsort_state_count",
     "radsort_state_truncate", "radsort_state_restart", "radsort_workspace_error",
-    "radsort_sort_pairs_noalloc",
+    "radsort_sort_pairs_noalloc", "radsort_msd_sort_pairs",
 ]
 NOALLOC_SCRATCH_BYTES = 32 << 20  # RADSORT_NOALLOC_SCRATCH_BYTES
 SEG_CLASSES = 32
@@ -83,6 +83,7 @@ def load(path: str | None = None):
     op = ctypes.POINTER(Opts)
     sig = {
         "radsort_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
+        "radsort_msd_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
         "radsort_sort_pairs_noalloc": (i32, [vp, vp, u64, i32, i32, i32, ctypes.c_uint32,
                                              ctypes.c_uint32, vp]),
         "radsort_sort": (i32, [vp, u64, i32, i32, vp]),
@@ -190,6 +191,22 @@ def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, works
               | (F_SHARED if shared else 0) | (F_SEQ_DRAWS if seq_draws else 0))
     with _device(keys):
         rc = load().radsort_sort_pairs(
+            ctypes.c_void_p(keys.data_ptr()),
+            ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
+            keys.numel(), kb, vb, digit_bits, ctypes.byref(o), _stream(stream, keys.device))
+    _check(rc)
+    return keys, payload
+
+
+def msd_sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, check=False,
+              shared=False):
+    """The MSD-first split (radsort_msd_sort_pairs): a Radsort round on the top
+    digit, finalize, then every top-digit group sorted by the remaining digits as
+    one batch.  Waits for the stream once, between the two phases."""
+    kb, vb = _validate(keys, payload)
+    o = _opts(block_elems, None, (F_CHECK if check else 0) | (F_SHARED if shared else 0))
+    with _device(keys):
+        rc = load().radsort_msd_sort_pairs(
             ctypes.c_void_p(keys.data_ptr()),
             ctypes.c_void_p(payload.data_ptr() if payload is not None else None),
             keys.numel(), kb, vb, digit_bits, ctypes.byref(o), _stream(stream, keys.device))

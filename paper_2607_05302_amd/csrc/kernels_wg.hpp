@@ -102,7 +102,7 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
     __shared__ uint32_t Pidx[sigma], Plen[sigma], Pnidx[sigma], Pnlen[sigma];
     __shared__ uint32_t bphys[NBLK], blenT[NBLK];
     __shared__ uint32_t wfill[WAVES];
-    __shared__ uint32_t sh_arr, sh_f, sh_fout, sh_F, sh_tfill;
+    __shared__ uint32_t sh_arr, sh_f, sh_fout, sh_F, sh_tfill, sh_skip;
     __shared__ uint32_t visited[(kWgMaxBlocks + 31) / 32];
 
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -176,9 +176,10 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
             const uint32_t shift = kWgBits * r;
             // closed forms (reading G5) from the round's counts
             if (tid == 0) {
-                uint32_t run = 0;
+                uint32_t run = 0, trivial = 0;
                 for (uint32_t d = 0; d < sigma; d++) {
                     const uint32_t cnt = hist[nt - 1 - r][d];
+                    trivial |= cnt == n;
                     const uint32_t c = 1 + (cnt >> log2b);
                     S[d] = sigma + run;
                     Pnidx[d] = sigma + run + c - 1;
@@ -188,8 +189,13 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
                 }
                 sh_fout = sigma + run;
                 sh_F = 0;
+                sh_skip = trivial;
             }
             __syncthreads();
+            // every element has the same digit at this position: the stable round
+            // would leave the logical sequence as it is, so it is left out (the state
+            // of the previous round stays, which finalize takes as it is)
+            if (sh_skip) continue;
             const uint32_t f_in = sh_f;
             const uint32_t tiles = (((f_in - sigma) << log2b) + E - 1) / E;
             for (uint32_t tile = 0; tile < tiles; tile++) {

@@ -318,6 +318,7 @@ struct radsort_state {
     bool is_setup = false;
     bool dynamic = false;      // launch forms that need no co-residency (shared GPU)
     bool seq_draws = false;    // draws in the sequential pool order (RADSORT_F_SEQ_DRAWS)
+    int msd_shift = -1;        // >= 0: the rounds sort the digit at this shift (MSD split)
 
     uint32_t* u32(uint64_t off) const { return (uint32_t*)(ws + off); }
     uint32_t* pi(int which) const { return u32(which ? L.pi1 : L.pi0); }
@@ -553,6 +554,7 @@ template <int KB, int VB> struct Ops {
         const uint32_t r = st->rounds_done;
         const uint32_t t = g.nt - 1 - r;  // key position of this round
         TileArgs<KB, VB> a{};
+        (void)t;
         a.Ak = (K*)st->keys;
         a.Av = (V*)st->vals;
         a.Tk = (K*)(st->ws + st->L.Tk);
@@ -567,7 +569,7 @@ template <int KB, int VB> struct Ops {
         a.done = (uint32_t*)(st->ws + st->L.done);
         a.err = st->err();
         a.tile_ctr = a.done + g.ring_w;  // zeroed with the ring
-        a.shift = g.bits * (g.nt - 1 - t);
+        a.shift = st->msd_shift >= 0 ? (uint32_t)st->msd_shift : g.bits * r;
         a.bits = g.bits;
         a.log2b = g.log2b;
         a.npi = g.npi;
@@ -1417,6 +1419,73 @@ int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
 }
 
 }  // extern "C"
+
+// ---- MSD-first split (Sec. 4.3, last paragraph) ------------------------------------
+//
+// One Radsort round on the most significant digit, finalized, leaves the array
+// grouped by that digit (stably); each group is then an independent sort over the
+// remaining digits, run as one batch of arrays by radsort_sort_segments (the
+// digit that is now constant in every group costs no round there).  The group
+// boundaries come from the digit totals that the round's counting pass leaves in
+// the last row of the super-tile table, read back to the host before finalize
+// reuses that memory.
+int radsort_msd_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
+                           int payload_bytes, int digit_bits, const radsort_opts* opts,
+                           void* stream)
+{
+    int rc = check_args(keys, payload, n, payload_bytes);
+    if (rc) return rc;
+    if (opts && opts->workspace) return RADSORT_E_INVALID;  // the library sizes each phase
+    Geo g;
+    rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts);
+    if (rc) return rc;
+    if (n <= 1) return RADSORT_OK;
+    radsort_opts o = opts ? *opts : radsort_opts{};
+    o.flags &= ~(uint32_t)RADSORT_F_TIMING;
+    radsort_state* st = nullptr;
+    rc = radsort_state_create(&st, keys, payload, n, key_bytes, payload_bytes, digit_bits, &o);
+    if (rc) return rc;
+    st->dynamic = (o.flags & RADSORT_F_SHARED) || g.b <= 1024;
+    st->msd_shift = (int)(g.bits * (g.nt - 1));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint32_t> tot(g.sigma, 0);
+    rc = radsort_state_setup(st, s);
+    if (!rc) rc = radsort_state_round(st, s);
+    if (!rc && hipMemcpyAsync(tot.data(), st->u32(st->L.stcnt) + (uint64_t)g.supers * g.sigma,
+                              4ull * g.sigma, hipMemcpyDeviceToHost, s) != hipSuccess)
+        rc = RADSORT_E_DEVICE;
+    if (!rc) rc = radsort_state_finalize(st, s);
+    if (!rc) rc = read_err(st, s, nullptr);  // waits: the totals are on the host
+    const uint64_t radsort_ws = st->L.total;
+    radsort_state_destroy(st);
+    if (rc) return rc;
+    std::vector<uint64_t> off(g.sigma + 1, 0);
+    for (uint32_t d = 0; d < g.sigma; d++) off[d + 1] = off[d] + tot[d];
+    if (off[g.sigma] != n) return RADSORT_E_DEVICE;  // never for a consistent round
+    uint64_t* off_dev = nullptr;
+    hipError_t e = hipMalloc((void**)&off_dev, 8ull * (g.sigma + 1));
+    if (e != hipSuccess) {
+        g_last_hip = e;
+        return RADSORT_E_NOMEM;
+    }
+    rc = RADSORT_OK;
+    if (hipMemcpyAsync(off_dev, off.data(), 8ull * (g.sigma + 1), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        rc = RADSORT_E_DEVICE;
+    radsort_opts so{};
+    so.flags = o.flags & RADSORT_F_CHECK;
+    if (!rc)
+        rc = radsort_sort_segments(keys, payload, off.data(), off_dev, g.sigma, key_bytes,
+                                   payload_bytes, nullptr, &so, stream);
+    const uint64_t seg_ws = g_stats.workspace_bytes;
+    (void)hipStreamSynchronize(s);  // off_dev is read by the segment kernels
+    (void)hipFree(off_dev);
+    g_stats.timed = 0;
+    g_stats.workspace_bytes = std::max<uint64_t>(radsort_ws, seg_ws + 8ull * (g.sigma + 1));
+    g_stats.input_bytes = n * (uint64_t)(key_bytes + payload_bytes);
+    g_stats.rounds = g.nt;
+    return rc;
+}
 
 // ---- the allocation-free entry point ----------------------------------------------
 //
