@@ -58,6 +58,46 @@ def measured_traffic(n, elem_bytes, b):
     return t.get("bytes_per_launch")
 
 
+def host_cpu() -> dict:
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def library_stable_sort(keys_np, target_s):
+    """numpy's stable argsort (one host thread) on the first keys of the same input,
+    with the payload gathered by the permutation: the library sort beside the
+    oracle, on a sample sized for about target_s seconds."""
+    import numpy as np
+
+    m = 1 << 20
+    t = time.perf_counter()
+    np.argsort(keys_np[:m], kind="stable")
+    per_key = (time.perf_counter() - t) / m
+    m = int(min(len(keys_np), max(1 << 20, target_s / per_key)))
+    m = 1 << (m.bit_length() - 1)
+    k = keys_np[:m]
+    t = time.perf_counter()
+    o = np.argsort(k, kind="stable")
+    ks, vs = k[o], o.astype(np.uint32)
+    dt = time.perf_counter() - t
+    del ks, vs
+    return {"value": m / dt, "unit": "keys/s", "cores": 1,
+            "kind": "numpy.argsort(kind='stable') + gather",
+            "sample": f"first {m} keys of the same input (2^{m.bit_length() - 1}), {dt:.2f} s"}
+
+
 def cpu_baseline(keys_np, target_s, b):
     """The sequential C oracle on a prefix of the same input (1 host thread)."""
     import numpy as np
@@ -78,7 +118,9 @@ def cpu_baseline(keys_np, target_s, b):
     return {"value": m / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
             "sample": f"first {m} of the {len(keys_np)} keys (2^{m.bit_length() - 1}), "
                       f"uint32 keys + uint32 index payload, b={b}, 8-bit digits, sequential "
-                      f"C oracle (Alg. 2-7), {dt:.1f} s"}
+                      f"C oracle (Alg. 2-7), {dt:.1f} s",
+            "host": host_cpu(),
+            "library_stable_sort": library_stable_sort(keys_np, min(6.0, target_s / 2))}
 
 
 def main():
@@ -91,12 +133,15 @@ def main():
     ap.add_argument("--no-oop", action="store_true", help="skip the out-of-place baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--workload", choices=["single", "segments", "serving", "resort"],
+    ap.add_argument("--workload", choices=["single", "segments", "serving", "resort",
+                                           "structured", "msd"],
                     default="single",
                     help="segments: 4096 uint32 arrays of log-uniform sizes in one call; "
                          "serving: a stream of sort requests admitted by memory footprint; "
                          "resort: new keys written in place and sorted again from the same "
-                         "state, without finalize")
+                         "state, without finalize; structured: 2^30 uint64 keys, four "
+                         "skewed and structured inputs; msd: the MSD-first split beside "
+                         "the LSD sort at 2^28 uint32 pairs")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests in the trace")
     ap.add_argument("--rate", type=float, default=800.0, help="serving: offered requests/s")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device memory budget")
@@ -123,12 +168,17 @@ def main():
         return bench_serving(args)
     if args.workload == "resort":
         return bench_resort(args)
+    if args.workload == "structured":
+        return bench_structured(args)
+    if args.workload == "msd":
+        return bench_msd(args)
     n = 1 << args.log2n
     b, bits, kb, vb = args.block, 8, 4, 4
+    seed = workloads.SEED_SMALL if args.log2n == 20 else workloads.SEED_LARGE
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log(f"bench: generating n=2^{args.log2n} uniform uint32 keys")
-    keys_np = workloads.uniform(workloads.SEED_LARGE, n, 4)
+    keys_np = workloads.uniform(seed, n, 4)
     keys0 = torch.from_numpy(keys_np.view(np.int32)).to(dev)
     vals0 = torch.arange(n, dtype=torch.int32, device=dev)
     keys = torch.empty_like(keys0)
@@ -196,6 +246,24 @@ def main():
             "peak_extra_frac_of_input": oop_bytes / (n * (kb + vb)),
         }
 
+    # the practical HBM ceiling: the library's streaming copy of the same bytes
+    # (keys and payload: one read and one write of n (s_k + s_v) bytes)
+    csrc = torch.empty(n * (kb + vb) // 4, dtype=torch.int32, device=dev)
+    cdst = torch.empty_like(csrc)
+    for _ in range(3):
+        radsort.copy_(cdst, csrc)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        radsort.copy_(cdst, csrc)
+    c1.record(stream)
+    c1.synchronize()
+    copy_ms = c0.elapsed_time(c1) / 10
+    copy_gbps = 2 * n * (kb + vb) / (copy_ms / 1e3) / 1e9
+    del csrc, cdst
+    log(f"bench: streaming copy of {n * (kb + vb)} bytes: {copy_ms:.3f} ms, {copy_gbps:.0f} GB/s")
+
     if args.copy_calibration:
         # a plain copy of known size: the HBM counters of this kernel give the scale
         src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
@@ -227,7 +295,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"radsort n=2^{args.log2n} uint32 keys uniform (splitmix64 seed "
-                        f"0x5EED0002) + uint32 index payload, 8-bit digits, b={b}",
+                        f"{seed:#x}) + uint32 index payload, 8-bit digits, b={b}",
             "n": n, "key_bytes": kb, "payload_bytes": vb, "digit_bits": bits,
             "block_elems": b,
         },
@@ -238,6 +306,9 @@ def main():
             "alg_bytes_per_launch": alg_bytes, "launch_ms": per_round,
         },
         "hbm_gbps_whole_sort": 4 * alg_bytes / (mean_ms / 1e3) / 1e9,
+        "copy_ceiling": {"gbps": copy_gbps, "ms": copy_ms,
+                         "kernel": "k_stream_copy (radsort_copy), 16-byte words",
+                         "round_frac_of_copy": achieved / copy_gbps},
         "phases_ms": {
             "setup": float(np.mean([s["setup_ms"] for s in stats])),
             "rounds": round_ms,
@@ -419,6 +490,148 @@ def resort_multiplier(step: int) -> int:
     """The odd multiplier of step `step`: key = payload * m mod 2^32 (as int32)."""
     m = ((0x9E3779B1 + step * 0x632BE5A6) | 1) & 0xFFFFFFFF
     return m - (1 << 32) if m >= 1 << 31 else m
+
+
+STRUCT_METRIC = "keys/s, uint64 keys only, n=2^30, 8-bit digits (8 rounds), b=1024: " \
+                "Zipf(1.1) over 2^16 values, all equal, sorted, low 20 bits random"
+
+
+def bench_structured(args):
+    """The four skewed and structured uint64 inputs at n = 2^30 (keys only), each
+    sorted steps times after a warm-up; per-round roofline at 16 bytes per element
+    (8-byte read + 8-byte write).  Each result is checked: keys ascending, and the
+    same sum of keys as the input (modulo 2^64).  The full check of these inputs
+    (stability and permutation through an index payload) is a GPU test."""
+    import numpy as np
+    import torch
+
+    import paper_2607_05302_amd as radsort
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log2n = 30 if args.log2n == 28 else args.log2n
+    n, b, bits = 1 << log2n, 1024, 8
+    ws = torch.empty(radsort.workspace_bytes(n, 8, 0, bits, b), dtype=torch.uint8, device=dev)
+    keys = torch.empty(n, dtype=torch.int64, device=dev)
+    steps = max(1, min(args.steps, 3))
+    per, total_keys, total_ms = {}, 0, 0.0
+    for dist in ["zipf", "equal", "sorted", "low20"]:
+        log(f"bench: structured {dist} n=2^{log2n}")
+        keys0 = workloads.make_t(dist, workloads.SEED_SKEWED, n, 8, dev)
+        ksum = int(keys0.sum())  # modulo 2^64, like the result's
+        keys.copy_(keys0)
+        radsort.sort_(keys, None, digit_bits=bits, block_elems=b, workspace=ws, check=True)
+        times, rounds = [], []
+        for _ in range(steps):
+            keys.copy_(keys0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            radsort.sort_(keys, None, digit_bits=bits, block_elems=b, workspace=ws, timing=True)
+            e1.record()
+            st = radsort.last_stats()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+            rounds.append(st["round_ms"])
+        flip = keys ^ (-(1 << 63))
+        ok = bool((flip[1:] >= flip[:-1]).all()) and int(keys.sum()) == ksum
+        del flip, keys0
+        torch.cuda.empty_cache()
+        rms = np.mean(np.array(rounds), axis=0)
+        achieved = 2 * n * 8 / (rms / 1e3) / 1e9
+        per[dist] = {"ms_per_sort": float(np.mean(times)), "keys_per_s": n / (np.mean(times) / 1e3),
+                     "round_ms": [float(x) for x in rms],
+                     "round_gbps": [float(x) for x in achieved],
+                     "round_frac": [float(x / HBM_PEAK_GBS) for x in achieved],
+                     "finalize_ms": float(st["finalize_ms"]), "verified": ok}
+        total_keys += n * len(times)
+        total_ms += float(np.sum(times))
+        log(f"bench: {dist}: {np.mean(times):.2f} ms per sort, verified {ok}")
+    ws_bytes = ws.numel()
+    mean_ms = total_ms / (total_keys / n)
+    all_rounds = np.array([r for d in per.values() for r in d["round_ms"]])
+    out = {
+        "metric": STRUCT_METRIC, "value": total_keys / (total_ms / 1e3), "unit": "keys/s",
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": mean_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"radsort n=2^{log2n} uint64 keys only, four inputs (seed "
+                               f"0x5EED0003), 8-bit digits, b={b}",
+                   "n": n, "key_bytes": 8, "payload_bytes": 0, "digit_bits": bits,
+                   "block_elems": b},
+        "roofline": {"bound": "hbm", "achieved": float(2 * n * 8 / (all_rounds.mean() / 1e3) / 1e9),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": float(2 * n * 8 / (all_rounds.mean() / 1e3) / 1e9 / HBM_PEAK_GBS),
+                     "traffic": None, "kernel": "k_round (one sort round, Alg. 5)",
+                     "alg_bytes_per_launch": 2 * n * 8, "launch_ms": float(all_rounds.mean())},
+        "inputs": per,
+        "peak_extra_bytes": ws_bytes, "peak_extra_frac_of_input": ws_bytes / (n * 8),
+        "verified": all(d["verified"] for d in per.values()),
+    }
+    print(json.dumps(out), flush=True)
+
+
+MSD_METRIC = "keys/s, MSD-first split (top-digit round + batched per-group sort), " \
+             "uint32 n=2^28 + uint32 index, beside the LSD Radsort"
+
+
+def bench_msd(args):
+    """The MSD-first split (radsort_msd_sort_pairs) and the LSD Radsort on the same
+    2^28 uint32 pairs; both results are checked."""
+    import numpy as np
+    import torch
+
+    import paper_2607_05302_amd as radsort
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, b, bits = 1 << args.log2n, args.block, 8
+    keys0 = workloads.uniform_t(workloads.SEED_LARGE, n, 4, dev)
+    vals0 = torch.arange(n, dtype=torch.int32, device=dev)
+    keys, vals = torch.empty_like(keys0), torch.empty_like(vals0)
+    res = {}
+    for name, fn in [("msd", radsort.msd_sort_), ("lsd", radsort.sort_)]:
+        log(f"bench: {name}")
+        keys.copy_(keys0)
+        vals.copy_(vals0)
+        fn(keys, vals, digit_bits=bits, block_elems=b, check=True)
+        times = []
+        for _ in range(max(1, args.steps)):
+            keys.copy_(keys0)
+            vals.copy_(vals0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn(keys, vals, digit_bits=bits, block_elems=b)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        extra = radsort.last_stats()["workspace_bytes"]
+        k = keys.to(torch.int64) & 0xFFFFFFFF
+        v = vals.to(torch.int64)
+        ok = bool((k[1:] >= k[:-1]).all())
+        eq = k[1:] == k[:-1]
+        ok &= bool((v[1:][eq] > v[:-1][eq]).all())
+        ok &= bool(((keys0.to(torch.int64) & 0xFFFFFFFF)[v] == k).all())
+        del k, v, eq
+        res[name] = {"ms_per_sort": float(np.mean(times)), "min_ms": float(np.min(times)),
+                     "keys_per_s": n / (np.mean(times) / 1e3), "peak_extra_bytes": int(extra),
+                     "peak_extra_frac_of_input": extra / (n * 8), "verified": ok}
+        log(f"bench: {name}: {np.mean(times):.2f} ms, extra {extra} bytes, verified {ok}")
+    out = {
+        "metric": MSD_METRIC, "value": res["msd"]["keys_per_s"], "unit": "keys/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": res["msd"]["ms_per_sort"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"MSD-first split, n=2^{args.log2n} uint32 keys uniform (seed "
+                               f"0x5EED0002) + uint32 index, 8-bit digits, b={b} (host wall "
+                               f"clock: the call waits once between its phases)",
+                   "n": n, "key_bytes": 4, "payload_bytes": 4, "digit_bits": bits,
+                   "block_elems": b},
+        "msd": res["msd"], "lsd": res["lsd"],
+        "verified": res["msd"]["verified"] and res["lsd"]["verified"],
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_resort(args):

@@ -297,6 +297,13 @@ int radsort_state_dims(const radsort_state* st, uint32_t* npi, uint32_t* sigma,
 /* Frees the state and the workspace it allocated (call after the stream is done). */
 int radsort_state_destroy(radsort_state* st);
 
+/* A plain device-to-device copy of `bytes` (16-byte aligned device pointers that do
+ * not overlap), enqueued on `stream`: the streaming-copy rate is the practical HBM
+ * ceiling against which the sort's passes are measured (the paper's parallel sort
+ * is bounded by the memory channels, Sec. 4.3).  Returns RADSORT_E_INVALID for a
+ * null or unaligned pointer with bytes > 0. */
+int radsort_copy(void* dst, const void* src, uint64_t bytes, void* stream);
+
 /* MSD-first split (Sec. 4.3, last paragraph): one Radsort round on the most
  * significant digit, then finalize, which leaves the array grouped by that digit;
  * then every group is sorted by the remaining digits as one batch of independent

@@ -34,7 +34,7 @@ ABI = [
     "radsort_sort_segments", "radsort_segments_workspace_bytes",
     "radsort_state_blocks", "radsort_state_planes", "radsort_state_count",
     "radsort_state_truncate", "radsort_state_restart", "radsort_workspace_error",
-    "radsort_sort_pairs_noalloc", "radsort_msd_sort_pairs",
+    "radsort_sort_pairs_noalloc", "radsort_msd_sort_pairs", "radsort_copy",
 ]
 NOALLOC_SCRATCH_BYTES = 32 << 20  # RADSORT_NOALLOC_SCRATCH_BYTES
 SEG_CLASSES = 32
@@ -84,6 +84,7 @@ def load(path: str | None = None):
     sig = {
         "radsort_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
         "radsort_msd_sort_pairs": (i32, [vp, vp, u64, i32, i32, i32, op, vp]),
+        "radsort_copy": (i32, [vp, vp, u64, vp]),
         "radsort_sort_pairs_noalloc": (i32, [vp, vp, u64, i32, i32, i32, ctypes.c_uint32,
                                              ctypes.c_uint32, vp]),
         "radsort_sort": (i32, [vp, u64, i32, i32, vp]),
@@ -196,6 +197,20 @@ def sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, works
             keys.numel(), kb, vb, digit_bits, ctypes.byref(o), _stream(stream, keys.device))
     _check(rc)
     return keys, payload
+
+
+def copy_(dst, src, stream=None):
+    """dst[:] = src[:] by the library's streaming copy kernel (radsort_copy); both
+    contiguous device tensors of the same size in bytes."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (dst.is_contiguous() and
+                                                           src.is_contiguous()):
+        raise ValueError("copy_ needs contiguous tensors of equal size")
+    with _device(src):
+        rc = load().radsort_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                 nbytes, _stream(stream, src.device))
+    _check(rc)
+    return dst
 
 
 def msd_sort_(keys, payload=None, digit_bits=8, block_elems=1024, stream=None, check=False,

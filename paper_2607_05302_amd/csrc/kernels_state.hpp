@@ -14,6 +14,31 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t v)
         p[i] = v;
 }
 
+// A plain streaming copy of 16-byte words (the practical HBM ceiling the sort is
+// measured against): every thread moves 4 words per step, all 4 loads issued
+// before the stores, grid-stride over the buffer.  The bytes that do not fill a
+// 16-byte word are copied by the first threads one byte each.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(u32x4* __restrict__ dst,
+                                                     const u32x4* __restrict__ src,
+                                                     uint64_t words, uint8_t* __restrict__ dtail,
+                                                     const uint8_t* __restrict__ stail,
+                                                     uint32_t tail)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < words; i += 4 * stride) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < 4; u++) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+    }
+    for (; i < words; i += stride) dst[i] = src[i];
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < tail) dtail[t] = stail[t];
+}
+
 // Histograms of every key position in one pass over the keys (the first loop
 // of Alg. 1, taken for all positions up front as the paper's "generic" variant
 // does, Sec. 5).  hist[t * sigma + c] counts key(x, t) = c, t = 0 the most

@@ -1312,6 +1312,26 @@ int radsort_last_stats(radsort_stats* out)
     return RADSORT_OK;
 }
 
+int radsort_copy(void* dst, const void* src, uint64_t bytes, void* stream)
+{
+    if (bytes && (!dst || !src)) return RADSORT_E_INVALID;
+    if (((uintptr_t)dst | (uintptr_t)src) & 15) return RADSORT_E_INVALID;
+    if (!bytes) return RADSORT_OK;
+    const uint64_t words = bytes / 16;
+    const uint32_t tail = (uint32_t)(bytes % 16);
+    int dev = 0, cus = 0;
+    RS_HIP(hipGetDevice(&dev));
+    RS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // 8 workgroups of 256 threads per CU, fewer when there is less to copy
+    const uint64_t want = (words + 4 * 256 - 1) / (4 * 256);
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 8ull * cus));
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, (hipStream_t)stream,
+                       (u32x4*)dst, (const u32x4*)src, words,
+                       (uint8_t*)dst + words * 16, (const uint8_t*)src + words * 16, tail);
+    RS_HIP(hipGetLastError());
+    return RADSORT_OK;
+}
+
 const char* radsort_strerror(int code)
 {
     switch (code) {
