@@ -29,11 +29,16 @@
 // blocks past f alone as unallocated, and F2 reads nothing from them.
 #pragma once
 
+#include <hip/hip_cooperative_groups.h>
+
 #include "common.hpp"
 
 namespace rs {
 
-constexpr uint32_t kFinJob = 1024;      // nodes per job of F1 (at most)
+#ifndef RS_FIN_JOB
+#define RS_FIN_JOB 1024
+#endif
+constexpr uint32_t kFinJob = RS_FIN_JOB;  // nodes per job of F1 (at most)
 constexpr uint32_t kFinCols = 256;      // columns of a block moved by one F1 workgroup
 constexpr uint32_t kFinDepth = 16;      // loads in flight per thread in F1
 constexpr uint32_t kScanTile = 4096;    // elements per workgroup of the device scan
@@ -532,6 +537,155 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
     }
 }
 
+// F1 in one cooperative launch (one workgroup of kFinLdsThreads per compute unit,
+// all resident): workgroup g owns jobs g jpw .. g jpw + jpw - 1 of `job` nodes
+// each.  It first copies the heads of its jobs' pieces (the nodes another job
+// overwrites, as k_fin_save picks them) into its LDS, then every workgroup meets
+// at a grid barrier, then each moves its jobs' nodes as k_fin_move does, taking
+// the heads from LDS.  Jobs can be many and short without any temporary block in
+// global memory: jpw * 2 heads of b (s_k + s_v) bytes must fit the dynamic LDS.
+constexpr uint32_t kFinLdsThreads = 512;
+constexpr uint32_t kFinLdsBytes = 128u << 10;  // dynamic LDS for saved heads
+constexpr uint32_t kFinLdsJobMax = 1024;       // nodes per job held in LDS
+
+template <int KB, int VB, int VEC>
+__global__ __launch_bounds__(kFinLdsThreads) void k_fin_move_lds(
+    FinArgs<KB, VB> a, FinArrays f, const uint32_t* rank, const uint32_t* clen,
+    const uint32_t* M_ptr, uint32_t job, uint32_t jpw)
+{
+    using K = typename Cols<typename UInt<KB>::T, VEC>::type;
+    using V = typename Cols<typename Payload<VB>::T, VEC>::type;
+    using KE = typename UInt<KB>::T;
+    using VE = typename Payload<VB>::T;
+    extern __shared__ __align__(16) uint8_t saved[];
+    __shared__ uint32_t sord[kFinLdsJobMax];
+    // loads in flight per thread (twice the threads of k_fin_move, half the depth)
+    constexpr uint32_t DEPTH = VEC == 1 ? kFinDepth : (KB + VB <= 8 ? 8u : 4u);
+    const uint32_t M = min(*M_ptr, a.npi), b = 1u << a.log2b, log2b = a.log2b;
+    const uint32_t two_sigma = 2 * a.sigma, tid = threadIdx.x;
+    KE* const hk_base = (KE*)saved;                                   // 2 jpw key blocks
+    VE* const hv_base = (VE*)(saved + 2ull * jpw * ((uint64_t)b * KB)); // then payload
+    auto safe = [&](uint32_t node) { return node < a.npi ? node : 0u; };
+
+    // ---- save the heads of every job of this workgroup -------------------------------
+    for (uint32_t k = 0; k < jpw; k++) {
+        const uint32_t j = blockIdx.x * jpw + k;
+        if ((uint64_t)j * job >= M) break;
+        uint32_t h[2];
+        job_heads(f.ord, rank, clen, j, job, M, a.npi, h[0], h[1]);
+        for (int q = 0; q < 2; q++) {
+            if (h[q] == ~0u || (h[q] & kGarbage)) continue;
+            if (h[q] >= a.npi) {  // never for a consistent order array
+                if (tid == 0) raise_error(a.err, kErrBounds);
+                continue;
+            }
+            const uint64_t slot = 2ull * k + q;
+            const KE* src = blockat(a.Ak, a.Tk, h[q], two_sigma, log2b);
+            for (uint32_t c = tid; c < b; c += kFinLdsThreads) hk_base[(slot << log2b) + c] = src[c];
+            if constexpr (VB != 0) {
+                const VE* sv = blockat(a.Av, a.Tv, h[q], two_sigma, log2b);
+                for (uint32_t c = tid; c < b; c += kFinLdsThreads)
+                    hv_base[(slot << log2b) + c] = sv[c];
+            }
+        }
+    }
+    // every head of every job is read before any job writes a block
+    __builtin_amdgcn_s_waitcnt(0);
+    cooperative_groups::this_grid().sync();
+
+    // ---- move the jobs' nodes ------------------------------------------------------------
+    for (uint32_t k = 0; k < jpw; k++) {
+        const uint32_t j = blockIdx.x * jpw + k;
+        const uint32_t i0 = j * job;
+        if (i0 >= M) break;
+        const uint32_t i1 = min(M, i0 + job);
+        __syncthreads();  // the previous job is done with sord
+        for (uint32_t i = i0 + tid; i < i1; i += kFinLdsThreads) sord[i - i0] = f.ord[i];
+        __syncthreads();
+        auto ord_at = [&](uint32_t i) { return i >= i0 && i < i1 ? sord[i - i0] : f.ord[i]; };
+        for (uint32_t col0 = 0; col0 < b; col0 += kFinLdsThreads * VEC) {
+            const uint32_t col = col0 + tid * VEC;
+            const bool active = col < b;  // b is a multiple of VEC
+            auto addr_k = [&](uint32_t node) {
+                return (K*)(blockat(a.Ak, a.Tk, safe(node), two_sigma, log2b) + col);
+            };
+            auto addr_v = [&](uint32_t node) {
+                return (V*)(blockat(a.Av, a.Tv, safe(node), two_sigma, log2b) + col);
+            };
+            uint32_t i = i0;
+            while (i < i1) {
+                const uint32_t p = sord[i - i0] & ~kGarbage;
+                if (p >= a.npi) {  // never for a consistent order array
+                    if (tid == 0) raise_error(a.err, kErrBounds);
+                    return;
+                }
+                const uint32_t r = rank[p], L = clen[p], cb = i - r;  // cycle base in ord
+                if (r >= L || cb + L > M) {
+                    if (tid == 0) raise_error(a.err, kErrBounds);
+                    return;
+                }
+                const uint32_t e = min(i1, cb + L);  // piece covers ord[i .. e)
+                const uint32_t ra = r, rb = r + (e - i);
+                const bool whole = ra == 0 && rb == L;
+                K hk{};
+                V hv{};
+                const uint32_t head = sord[i - i0];
+                const bool head_garbage = head & kGarbage;
+                if (active && !head_garbage) {
+                    if (whole) {
+                        hk = *addr_k(head & ~kGarbage);
+                        if constexpr (VB != 0) hv = *addr_v(head & ~kGarbage);
+                    } else {
+                        const uint64_t slot = 2ull * k + (i == i0 ? 0 : 1);
+                        hk = *(const K*)(hk_base + (slot << log2b) + col);
+                        if constexpr (VB != 0) hv = *(const V*)(hv_base + (slot << log2b) + col);
+                    }
+                }
+                // node(x + 1 mod L) <- node(x) for x = rb-1 down to ra+1, in batches
+                uint32_t x = rb;
+                while (x > ra + 1) {
+                    const uint32_t cnt = min(DEPTH, x - (ra + 1));
+                    K bk[DEPTH];
+                    V bv[DEPTH];
+                    uint32_t src[DEPTH];
+#pragma unroll
+                    for (uint32_t u = 0; u < DEPTH; u++) {
+                        if (u < cnt) {
+                            src[u] = ord_at(cb + x - 1 - u);
+                            if (active && !(src[u] & kGarbage)) {
+                                bk[u] = *addr_k(src[u] & ~kGarbage);
+                                if constexpr (VB != 0) bv[u] = *addr_v(src[u] & ~kGarbage);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < DEPTH; u++) {
+                        if (u < cnt) {
+                            const uint32_t rd = x - u;  // destination rank (mod L)
+                            const uint32_t dst = ord_at(cb + (rd == L ? 0 : rd)) & ~kGarbage;
+                            if (active && !(src[u] & kGarbage)) {
+                                *addr_k(dst) = bk[u];
+                                if constexpr (VB != 0) *addr_v(dst) = bv[u];
+                            }
+                        }
+                    }
+                    x -= cnt;
+                }
+                // node(ra + 1 mod L) <- head
+                {
+                    const uint32_t rd = ra + 1;
+                    const uint32_t dst = ord_at(cb + (rd == L ? 0 : rd)) & ~kGarbage;
+                    if (active && !head_garbage) {
+                        *addr_k(dst) = hk;
+                        if constexpr (VB != 0) *addr_v(dst) = hv;
+                    }
+                }
+                i = e;
+            }
+        }
+    }
+}
+
 // ---- F2: ordered compaction -----------------------------------------------------------
 
 // gap[i] = sum of (b - len) over partial entries 0 .. i-1 of P; gap[sigma] = total
@@ -690,9 +844,12 @@ inline void fin_scan(uint32_t* a, uint32_t count, uint32_t* sums, hipStream_t s)
 constexpr int kCompactThreads = 512;
 template <int KB, int VB> constexpr int fin_chunk() { return (KB + VB >= 12) ? 4096 : 8192; }
 
-// compact_grid = 0 selects the dynamic compaction (one workgroup per chunk)
+// compact_grid = 0 selects the dynamic compaction (one workgroup per chunk);
+// lds_grid = 0 the two-kernel F1 with heads saved in global memory, else the
+// cooperative F1 on lds_grid workgroups (one per compute unit)
 template <int KB, int VB>
-int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
+int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_grid,
+                      hipStream_t s)
 {
     const uint32_t npi = a.npi, b = 1u << a.log2b;
     FinArrays f = fin_arrays(a.scratch, npi, a.n, a.spare_pi, a.spare_blen);
@@ -738,11 +895,30 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
                            dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
                            dim3(256), 0, s, f.flags, f.nflags, 0u);
     }
-    const uint32_t jobs = (npi + a.job - 1) / a.job;
-    hipLaunchKernelGGL((k_fin_save<KB, VB>), dim3(jobs), dim3(256), 0, s, a, f, rank, clen, M_ptr);
     // four columns per thread when every block start is 16-byte aligned
     const bool wide = b >= 64 && (((uintptr_t)a.Ak | (uintptr_t)a.Av | (uintptr_t)a.Tk |
                                    (uintptr_t)a.Tv | (uintptr_t)f.temps) & 15) == 0;
+    const uint64_t head_bytes = (uint64_t)b * (KB + VB);
+    const uint32_t jpw = (uint32_t)std::min<uint64_t>(8, kFinLdsBytes / (2 * head_bytes));
+    if (lds_grid && jpw > 0) {
+        // the cooperative form: jobs of at most kFinLdsJobMax nodes, jpw per workgroup
+        uint32_t job = (uint32_t)((npi + (uint64_t)lds_grid * jpw - 1) / ((uint64_t)lds_grid * jpw));
+        job = std::max<uint32_t>(16, std::min<uint32_t>(job, kFinLdsJobMax));
+        const uint32_t grid = std::min<uint32_t>(lds_grid, (npi + job * jpw - 1) / (job * jpw));
+        const uint32_t lds = (uint32_t)(2 * jpw * head_bytes);
+        void* args[] = {(void*)&a, (void*)&f, (void*)&rank, (void*)&clen, (void*)&M_ptr,
+                        (void*)&job, (void*)&jpw};
+        const void* kern = wide ? (const void*)&k_fin_move_lds<KB, VB, 4>
+                                : (const void*)&k_fin_move_lds<KB, VB, 1>;
+        if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+            return -1;
+        if (hipLaunchCooperativeKernel(kern, dim3(grid), dim3(kFinLdsThreads), args, lds, s) !=
+            hipSuccess)
+            return -1;
+    } else {
+    const uint32_t jobs = (npi + a.job - 1) / a.job;
+    hipLaunchKernelGGL((k_fin_save<KB, VB>), dim3(jobs), dim3(256), 0, s, a, f, rank, clen, M_ptr);
     if (wide) {
         const uint32_t slices = (b + 4 * kFinCols - 1) / (4 * kFinCols);
         hipLaunchKernelGGL((k_fin_move<KB, VB, 4>), dim3(jobs, slices), dim3(kFinCols), 0, s, a, f,
@@ -751,6 +927,7 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, hipStream_t s)
         const uint32_t slices = (b + kFinCols - 1) / kFinCols;
         hipLaunchKernelGGL((k_fin_move<KB, VB, 1>), dim3(jobs, slices), dim3(kFinCols), 0, s, a, f,
                            rank, clen, M_ptr);
+    }
     }
     // F2: compaction
     const uint64_t positions = (a.n >> a.log2b) << a.log2b;

@@ -317,6 +317,7 @@ struct radsort_state {
     bool truncated = false;
     bool is_setup = false;
     bool dynamic = false;      // launch forms that need no co-residency (shared GPU)
+    bool shared = false;       // other work shares the GPU: no cooperative launch at all
     bool seq_draws = false;    // draws in the sequential pool order (RADSORT_F_SEQ_DRAWS)
     int msd_shift = -1;        // >= 0: the rounds sort the digit at this shift (MSD split)
 
@@ -637,14 +638,22 @@ template <int KB, int VB> struct Ops {
         a.spare_pi = st->pi(st->cur ^ 1);
         a.spare_blen = st->u32(st->L.blen);
         g_timer.mark(kFinBegin, 0, s);
-        int cap = 0;  // 0: the dynamic compaction
+        int cap = 0;       // 0: the dynamic compaction
+        uint32_t cus = 0;  // 0: F1 without a cooperative launch
         if (!st->dynamic) {
             const void* compact =
                 (const void*)&k_fin_compact<KB, VB, fin_chunk<KB, VB>(), kCompactThreads>;
             cap = resident_capacity(compact, kCompactThreads);
             if (cap <= 0) return RADSORT_E_DEVICE;
         }
-        int rc = finalize_parallel<KB, VB>(a, (uint32_t)cap, s) ? RADSORT_E_DEVICE : RADSORT_OK;
+        if (!st->shared) {
+            int dev = 0, n_cu = 0;
+            RS_HIP(hipGetDevice(&dev));
+            RS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+            cus = (uint32_t)n_cu;
+        }
+        int rc = finalize_parallel<KB, VB>(a, (uint32_t)cap, cus, s) ? RADSORT_E_DEVICE
+                                                                      : RADSORT_OK;
         g_timer.mark(kFinEnd, 0, s);
         return rc;
     }
@@ -972,6 +981,7 @@ int run_one(void* keys, void* vals, uint64_t n, int kb, int vb, SegChoice c, uin
     int rc = radsort_state_create(&st, keys, vals, n, kb, vb, (int)c.bits, &o);
     if (rc) return rc;
     st->dynamic = true;
+    st->shared = true;  // the lanes run concurrently: no cooperative launch
     rc = radsort_state_setup(st, s);
     for (uint32_t r = 0; !rc && r < st->g.nt; r++) rc = radsort_state_round(st, s);
     if (!rc) rc = radsort_state_finalize(st, s);
@@ -1204,6 +1214,7 @@ int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes, int
     // round, which costs most at small n); with larger blocks the persistent form,
     // whose workgroups overlap one tile's loads with the previous tile, is faster.
     st->dynamic = (opts && (opts->flags & RADSORT_F_SHARED)) || g.b <= 1024;
+    st->shared = opts && (opts->flags & RADSORT_F_SHARED);
     hipStream_t s = (hipStream_t)stream;
     const bool timing = opts && (opts->flags & RADSORT_F_TIMING);
     if (timing) g_timer.begin();
@@ -1466,6 +1477,7 @@ int radsort_msd_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes,
     rc = radsort_state_create(&st, keys, payload, n, key_bytes, payload_bytes, digit_bits, &o);
     if (rc) return rc;
     st->dynamic = (o.flags & RADSORT_F_SHARED) || g.b <= 1024;
+    st->shared = o.flags & RADSORT_F_SHARED;
     st->msd_shift = (int)(g.bits * (g.nt - 1));
     hipStream_t s = (hipStream_t)stream;
     std::vector<uint32_t> tot(g.sigma, 0);
@@ -1576,6 +1588,7 @@ int radsort_sort_pairs_noalloc(void* keys, void* payload, uint64_t n, int key_by
     st.seq_draws = flags & RADSORT_F_SEQ_DRAWS;
     // the launch forms that query no occupancy (the query's cache allocates)
     st.dynamic = true;
+    st.shared = true;
     hipStream_t s = (hipStream_t)stream;
     rc = radsort_state_setup(&st, s);
     for (uint32_t r = 0; !rc && r < st.g.nt; r++) rc = radsort_state_round(&st, s);
