@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--rate", type=float, default=800.0, help="serving: offered requests/s")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: device memory budget")
     ap.add_argument("--slots", type=int, default=8, help="serving: requests on the GPU at once")
+    ap.add_argument("--min-log2", type=float, default=12, help="serving: smallest size, log2")
+    ap.add_argument("--max-log2", type=float, default=28, help="serving: largest size, log2")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scales HBM counters)")
     args = ap.parse_args()
@@ -451,7 +453,7 @@ def bench_serving(args):
     from paper_2607_05302_amd import serve
 
     torch.cuda.set_device(0)
-    trace = serve.make_trace(SERVE_SEED, args.requests, args.rate)
+    trace = serve.make_trace(SERVE_SEED, args.requests, args.rate, args.min_log2, args.max_log2)
     res = {}
     for method in ("radsort", "oop"):
         srv = serve.Server(method, budget=args.budget_gb * 1e9, slots=args.slots)
@@ -466,8 +468,8 @@ def bench_serving(args):
     r = res["radsort"]
     out = {
         "metric": "sort serving: keys/s and p50/p99 latency, Poisson arrivals, sizes log-uniform "
-                  f"in [2^12, 2^28], 50/50 uint32/uint64 keys, {args.budget_gb:g} GB budget, "
-                  "Radsort vs out-of-place",
+                  f"in [2^{args.min_log2:g}, 2^{args.max_log2:g}], 50/50 uint32/uint64 keys, "
+                  f"{args.budget_gb:g} GB budget, Radsort vs out-of-place",
         "value": r["keys_per_s"], "unit": "keys/s", "n_gpus": 1, "steps": args.requests,
         "warmup": 8, "ms_per_step": r["span_ms"] / args.requests, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32/u64", "data": "synthetic",

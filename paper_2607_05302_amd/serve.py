@@ -171,49 +171,66 @@ class Server:
             done.record(stream)
         return keys, vals, ws, done
 
-    def _check(self, req: Request, keys, vals) -> bool:
-        """On the device, after the request's sort: keys ascending (unsigned), the
-        same multiset sums as the input keys drawn again from the request's seed,
-        and the index payload summing to n (n - 1) / 2.  A check, not a proof: it
-        catches lost, duplicated and misplaced records."""
+    def _check(self, req: Request, keys, vals, k_in, seen) -> bool:
+        """On the device, after the request's sort, the complete check of a stable
+        sort with an index payload: keys ascending (unsigned), equal keys in
+        ascending index, the payload a permutation of 0 .. n-1, and every key equal
+        to the input key at its index (the input drawn again from the request's
+        seed into ``k_in``; ``seen`` holds at least n flags)."""
         import torch
-        flip = torch.tensor(-(1 << 63), dtype=torch.int64, device=keys.device)
-        unsorted = torch.zeros((), dtype=torch.int64, device=keys.device)
-        ksum = torch.zeros((), dtype=torch.int64, device=keys.device)
-        vsum = torch.zeros((), dtype=torch.int64, device=keys.device)
-        # the input drawn again, piece by piece as draw_input draws it
-        k0 = torch.empty(min(req.n, DRAW_CHUNK), dtype=keys.dtype, device=keys.device)
+        n = req.n
         g = torch.Generator(device=keys.device)
         g.manual_seed(req.seed & 0x7FFFFFFFFFFFFFFF)
         lo_hi = (-(1 << 31), 1 << 31) if req.key_bytes == 4 else (-(1 << 63), (1 << 63) - 1)
-        for lo in range(0, req.n, DRAW_CHUNK):  # neighbouring pieces overlap by one key
-            hi = min(req.n, lo + DRAW_CHUNK)
-            k = keys[max(lo - 1, 0):hi]
-            k = (k.to(torch.int64) & 0xFFFFFFFF) if req.key_bytes == 4 else k ^ flip
-            unsorted += (k[1:] < k[:-1]).sum()
+        kin = k_in[:n * req.key_bytes // k_in.element_size()].view(keys.dtype)
+        for lo in range(0, n, DRAW_CHUNK):  # as draw_input draws it
+            hi = min(n, lo + DRAW_CHUNK)
             torch.randint(*lo_hi, (hi - lo,), generator=g, dtype=keys.dtype, device=keys.device,
-                          out=k0[:hi - lo])
-            ksum += k0[:hi - lo].sum(dtype=torch.int64) - keys[lo:hi].sum(dtype=torch.int64)
-            vsum += vals[lo:hi].sum(dtype=torch.int64)
-        return (int(unsorted.item()) == 0 and int(ksum.item()) == 0
-                and int(vsum.item()) == req.n * (req.n - 1) // 2)
+                          out=kin[lo:hi])
+        flip = torch.tensor(-(1 << 63), dtype=torch.int64, device=keys.device)
+        bad = torch.zeros((), dtype=torch.int64, device=keys.device)
+        seen_n = seen[:n]
+        seen_n.zero_()
+        for lo in range(0, n, DRAW_CHUNK):  # neighbouring pieces overlap by one record
+            hi = min(n, lo + DRAW_CHUNK)
+            a = max(lo - 1, 0)
+            k = keys[a:hi]
+            u = (k.to(torch.int64) & 0xFFFFFFFF) if req.key_bytes == 4 else k ^ flip
+            v = vals[a:hi].to(torch.int64)
+            bad += (u[1:] < u[:-1]).sum()                                   # ascending
+            bad += ((u[1:] == u[:-1]) & (v[1:] <= v[:-1])).sum()            # stable
+            vv = vals[lo:hi].to(torch.int64)
+            bad += ((vv < 0) | (vv >= n)).sum()
+            vc = vv.clamp(0, n - 1)
+            seen_n[vc] = True                                               # permutation
+            bad += (kin[vc] != keys[lo:hi]).sum()                           # its own key
+        bad += (~seen_n).sum()
+        return int(bad.item()) == 0
 
     def run(self, trace, keep=(), verify=False):
         """Serves the trace in real time.  Returns per-request latencies (ms, from
         arrival to the end of its sort on the GPU), the makespan, the sorted arrays
-        of the requests whose ids are in ``keep`` (on the host), and with verify the
+        of the requests whose ids are in ``keep`` (on the host), the number of
+        requests that waited for memory while a slot was free, and with verify the
         ids of the requests whose result failed `_check` (checked when each
         request completes, on its stream, which adds device work to the run)."""
         import torch
 
         import paper_2607_05302_amd as radsort
         keep = set(keep)
+        k_in = seen = None
+        if verify:  # scratch of the complete check, sized for the largest request
+            big = max((r.n for r in trace), default=1)
+            k_in = torch.empty(big * 8, dtype=torch.uint8, device=self.device)
+            seen = torch.empty(big, dtype=torch.bool, device=self.device)
         pending = collections.deque(sorted(trace, key=lambda r: r.arrival))
         queue = collections.deque()
         free = list(range(len(self.streams)))
         active = {}
         used, peak_used, peak_active = 0, 0, 0
-        out = {"latency_ms": {}, "kept": {}, "admit_wait_ms": {}, "bad": [], "device_errors": []}
+        waited = set()  # requests that found a free slot but not enough free memory
+        out = {"latency_ms": {}, "kept": {}, "admit_wait_ms": {}, "bad": [], "device_errors": [],
+               "memory_waits": 0}
         torch.cuda.synchronize(self.device)
         t0_ev = torch.cuda.Event(enable_timing=True)
         t0_ev.record(torch.cuda.current_stream(self.device))
@@ -233,7 +250,7 @@ class Server:
                         out["kept"][req.rid] = (keys.cpu().numpy(), vals.cpu().numpy())
                     if verify:
                         with torch.cuda.stream(self.streams[slot]):
-                            if not self._check(req, keys, vals):
+                            if not self._check(req, keys, vals, k_in, seen):
                                 out["bad"].append(req.rid)
                         if radsort.workspace_error(keys, vals, block_elems=self.block,
                                                    stream=self.streams[slot], workspace=ws,
@@ -250,7 +267,11 @@ class Server:
                     raise ValueError(f"request {queue[0].rid} needs {fp} bytes, more than the budget")
                 base = self.arena.alloc(fp)
                 if base is None:
-                    break  # first come, first served: wait for memory
+                    # first come, first served: a slot is free, the memory is not
+                    if queue[0].rid not in waited:
+                        waited.add(queue[0].rid)
+                        out["memory_waits"] += 1
+                    break
                 req = queue.popleft()
                 slot = free.pop()
                 out["admit_wait_ms"][req.rid] = (time.perf_counter() - t0 - req.arrival) * 1e3
@@ -284,6 +305,7 @@ def summarize(trace, out) -> dict:
         "peak_footprint_bytes": int(out["peak_footprint_bytes"]),
         "peak_active": int(out["peak_active"]),
         "mean_admit_wait_ms": float(np.mean(list(out["admit_wait_ms"].values()))),
+        "memory_waits": int(out.get("memory_waits", 0)),
         "wrong_results": len(out.get("bad", [])),
         "device_errors": len(out.get("device_errors", [])),
     }

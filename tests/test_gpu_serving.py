@@ -1,6 +1,7 @@
-"""The serving loop: each request's result is the same when it runs alone and
-when it runs in the mix (admitted by footprint, sharing the GPU with others),
-for Radsort and for the out-of-place baseline; small ones also match the oracle."""
+"""The serving loop: each request's result is the same when it runs alone (with
+the same method) and when it runs in the mix (admitted by footprint under a
+budget that makes requests wait for memory, sharing the GPU with others), for
+Radsort and for the out-of-place baseline; small ones also match the oracle."""
 import numpy as np
 import pytest
 
@@ -22,23 +23,32 @@ def drawn(req):
     return keys, vals
 
 
-def alone(req):
+def alone(req, method="radsort"):
     keys, vals = drawn(req)
-    radsort.sort_(keys, vals, check=True)
+    sort = radsort.sort_ if method == "radsort" else radsort.oop_sort_
+    sort(keys, vals, check=True)
     return keys.cpu().numpy(), vals.cpu().numpy()
 
 
 @pytest.mark.parametrize("method", ["radsort", "oop"])
 def test_results_alone_and_in_the_mix(method):
     trace = serve.make_trace(0x5E4, 14, rate=2e4, lo_log2=10, hi_log2=21)
-    budget = 6 * max(serve.footprint(r, method) for r in trace)  # forces waits for memory
+    # one large request among the small ones, and a mid-size one right after it
+    trace[5] = serve.Request(5, trace[5].arrival, (1 << 24) + 3, 8, trace[5].seed)
+    trace[6] = serve.Request(6, trace[6].arrival, 1 << 21, 8, trace[6].seed)
+    # the largest footprint and 5 % more: while the large request runs, the next
+    # one cannot fit although slots are free, so it waits for memory
+    big = max(serve.footprint(r, method) for r in trace)
+    budget = big + big // 20
+    assert serve.footprint(trace[6], method) > big // 20
     srv = serve.Server(method, budget=budget, slots=6)
     out = srv.run(trace, keep=[r.rid for r in trace])
     assert len(out["latency_ms"]) == len(trace)
     assert out["peak_footprint_bytes"] <= budget
+    assert out["memory_waits"] > 0, "no request waited for memory while a slot was free"
     for r in trace:
         mk, mv = out["kept"][r.rid]
-        ak, av = alone(r)
+        ak, av = alone(r, method)
         assert np.array_equal(mk, ak), f"keys of request {r.rid} differ"
         assert np.array_equal(mv, av), f"payload of request {r.rid} differs"
         if r.n <= 1 << 16:
@@ -69,8 +79,9 @@ def test_workspace_error_reads_clear_after_shared_sorts(method, n, kb):
 
 def test_concurrent_shared_sorts_are_right():
     """Eight slots of large uint64 and uint32 sorts at a high arrival rate: every
-    result checked on the device (sorted, key sum, payload sum) and every sort's
-    error word clear.  Tiles of a sort that shares the GPU can run far apart in
+    result checked completely on the device (ascending, stable, the payload a
+    permutation, every key the input key at its index) and every sort's error
+    word clear.  Tiles of a sort that shares the GPU can run far apart in
     time, which is when a block drawn by one tile and continued by later tiles must
     not be written before its old contents have been loaded."""
     trace = serve.make_trace(0x5E5, 48, rate=2e3, lo_log2=20, hi_log2=25)
