@@ -304,6 +304,10 @@ def summarize(trace, out) -> dict:
         "span_ms": float(span),
         "peak_footprint_bytes": int(out["peak_footprint_bytes"]),
         "peak_active": int(out["peak_active"]),
+        # requests on the GPU at once, averaged over the span: each is active from
+        # its admission to the end of its sort
+        "mean_active": float(sum(out["latency_ms"][r.rid] - out["admit_wait_ms"][r.rid]
+                                 for r in trace) / span),
         "mean_admit_wait_ms": float(np.mean(list(out["admit_wait_ms"].values()))),
         "memory_waits": int(out.get("memory_waits", 0)),
         "wrong_results": len(out.get("bad", [])),
