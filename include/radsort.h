@@ -74,9 +74,12 @@ typedef struct radsort_opts {
 #define RADSORT_MAX_ROUNDS 64
 
 /* Block size and digit width per size class for the arrays of radsort_sort_segments
- * that run the Radsort steps on streams (those above 4 423 680 elements): an array
- * of n elements takes the first class c with ceil(log2 n) <= max_log2n[c].
- * digit_bits must be 4, 8 or 11 and block_elems a power of two in [64, 65536]. */
+ * that run the Radsort steps on streams: an array of n elements takes the first class
+ * c with ceil(log2 n) <= max_log2n[c].  Arrays above 4 423 680 elements always run
+ * there; a smaller array (but above the whole-in-LDS limit of 8192, or 4096 for
+ * records of 12 bytes or more) runs there when its class has block_elems > 0, and on
+ * one workgroup of the batched kernel when block_elems = 0 or no class covers it.
+ * digit_bits must be 4, 8 or 11 and block_elems 0 or a power of two in [64, 65536]. */
 #define RADSORT_SEG_CLASSES 32
 typedef struct radsort_seg_tuning {
     uint32_t classes;

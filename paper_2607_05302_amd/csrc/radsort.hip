@@ -829,15 +829,32 @@ SegChoice seg_choice(const radsort_seg_tuning* t, uint64_t n)
     const uint32_t lg = (uint32_t)ilog2(n);
     if (t)
         for (uint32_t c = 0; c < t->classes && c < RADSORT_SEG_CLASSES; c++)
-            if (lg <= t->max_log2n[c]) return {t->block_elems[c], t->digit_bits[c]};
+            if (lg <= t->max_log2n[c] && t->block_elems[c]) return {t->block_elems[c], t->digit_bits[c]};
     const uint32_t b = std::min<uint32_t>(2048u, std::max<uint32_t>(64u, 1u << ((lg + 1) / 2)));
     return {b, 8u};
+}
+
+// The largest array the one-workgroup path takes: its limit, or lower when the
+// tuning's first class with block_elems > 0 starts below it (arrays from that class
+// on run on the lanes).  The host plan and the device list both use this bound.
+uint64_t seg_wg_hi(const radsort_seg_tuning* t, uint64_t se)
+{
+    uint64_t hi = wg_max_elems();
+    if (!t) return hi;
+    for (uint32_t c = 0; c < t->classes && c < RADSORT_SEG_CLASSES; c++) {
+        if (t->block_elems[c]) {
+            const uint64_t below = c ? (1ull << std::min<uint32_t>(t->max_log2n[c - 1], 40)) : se;
+            return std::max<uint64_t>(se, std::min<uint64_t>(hi, below));
+        }
+    }
+    return hi;
 }
 
 struct SegPlan {
     std::vector<uint32_t> large;  // indices of the arrays that run the Radsort steps
     std::vector<uint32_t> lane;   // lane of each of them
     std::vector<SegChoice> choice;
+    uint64_t wg_hi = 0;           // arrays of (small, wg_hi] elements take the one-workgroup path
     uint64_t lane_off[kSegLanes] = {}, lane_bytes[kSegLanes] = {};
     uint32_t wg_count = 0, wg_slots = 0;  // arrays of the one-workgroup path, workgroups
     uint64_t wg_off = 0, wg_slot_bytes = 0, wg_list_off = 0;
@@ -853,6 +870,7 @@ int make_seg_plan(SegPlan& P, const uint64_t* off, uint32_t nseg, int kb, int vb
                   const radsort_seg_tuning* tuning, const radsort_opts* opts)
 {
     const uint32_t se = small_elems(kb, vb);
+    P.wg_hi = seg_wg_hi(tuning, se);
     std::vector<std::pair<uint64_t, uint32_t>> big;
     for (uint32_t i = 0; i < nseg; i++) {
         if (off[i + 1] < off[i]) return RADSORT_E_INVALID;
@@ -862,7 +880,7 @@ int make_seg_plan(SegPlan& P, const uint64_t* off, uint32_t nseg, int kb, int vb
             P.any_small = true;
             continue;
         }
-        if (n <= wg_max_elems()) {
+        if (n <= P.wg_hi) {
             P.wg_count++;
             continue;
         }
@@ -954,7 +972,7 @@ template <int KB, int VB> struct DoWg {
         using C = WgCfg<KB, VB>;
         uint32_t* list = (uint32_t*)(ws + P.wg_list_off);
         hipLaunchKernelGGL(k_wg_list, dim3(1), dim3(1024), 0, s, offsets_dev, nseg,
-                           (uint64_t)small_elems(KB, VB), wg_max_elems(), list, P.wg_count);
+                           (uint64_t)small_elems(KB, VB), P.wg_hi, list, P.wg_count);
         hipLaunchKernelGGL((k_radsort_wg<KB, VB>), dim3(P.wg_slots), dim3(C::NT), 0, s,
                            (typename UInt<KB>::T*)keys, (typename Payload<VB>::T*)vals,
                            offsets_dev, nseg, (const uint32_t*)list, P.wg_count, claim,
@@ -1397,7 +1415,25 @@ int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
     // [2 + kSegLanes]: its claim counter
     uint32_t* err_small = (uint32_t*)ws;
     launch_fill(err_small, 3 + kSegLanes, 0, s);
-    if (P.any_small) {
+    // the lanes fork first, so that their sorts run beside the batched kernels on the
+    // caller's stream; they join back at the end
+    LaneStreams* L = nullptr;
+    if (!P.large.empty()) {
+        rc = lane_streams(&L);
+        if (!rc && hipEventRecord(L->fork, s) != hipSuccess) rc = RADSORT_E_DEVICE;
+        for (uint32_t l = 0; !rc && l < kSegLanes; l++)
+            if (hipStreamWaitEvent(L->s[l], L->fork, 0) != hipSuccess) rc = RADSORT_E_DEVICE;
+        const uint64_t kb = key_bytes, vb = payload_bytes;
+        for (size_t k = 0; !rc && k < P.large.size(); k++) {
+            const uint32_t i = P.large[k], l = P.lane[k];
+            void* kp = (uint8_t*)keys + offsets[i] * kb;
+            void* vp = payload ? (uint8_t*)payload + offsets[i] * vb : nullptr;
+            rc = run_one(kp, vp, offsets[i + 1] - offsets[i], key_bytes, payload_bytes,
+                         P.choice[k], ws + P.lane_off[l], P.lane_bytes[l], err_small + 1 + l,
+                         L->s[l]);
+        }
+    }
+    if (!rc && P.any_small) {
         rc = dispatch<DoSmall>(key_bytes, payload_bytes, keys, payload, offsets_dev, nseg,
                                err_small, s);
     }
@@ -1405,27 +1441,10 @@ int radsort_sort_segments(void* keys, void* payload, const uint64_t* offsets,
         rc = dispatch<DoWg>(key_bytes, payload_bytes, keys, payload, offsets_dev, nseg, P, ws,
                             err_small + 2 + kSegLanes, err_small + 1 + kSegLanes, s);
     }
-    if (!rc && !P.large.empty()) {
-        LaneStreams* L = nullptr;
-        rc = lane_streams(&L);
-        if (!rc) {
-            // fork the lanes from the caller's stream, join them back at the end
-            if (hipEventRecord(L->fork, s) != hipSuccess) rc = RADSORT_E_DEVICE;
-            for (uint32_t l = 0; !rc && l < kSegLanes; l++)
-                if (hipStreamWaitEvent(L->s[l], L->fork, 0) != hipSuccess) rc = RADSORT_E_DEVICE;
-            const uint64_t kb = key_bytes, vb = payload_bytes;
-            for (size_t k = 0; !rc && k < P.large.size(); k++) {
-                const uint32_t i = P.large[k], l = P.lane[k];
-                void* kp = (uint8_t*)keys + offsets[i] * kb;
-                void* vp = payload ? (uint8_t*)payload + offsets[i] * vb : nullptr;
-                rc = run_one(kp, vp, offsets[i + 1] - offsets[i], key_bytes, payload_bytes,
-                             P.choice[k], ws + P.lane_off[l], P.lane_bytes[l], err_small + 1 + l,
-                             L->s[l]);
-            }
-            for (uint32_t l = 0; l < kSegLanes; l++) {
-                if (hipEventRecord(L->join[l], L->s[l]) != hipSuccess && !rc) rc = RADSORT_E_DEVICE;
-                if (hipStreamWaitEvent(s, L->join[l], 0) != hipSuccess && !rc) rc = RADSORT_E_DEVICE;
-            }
+    if (L) {
+        for (uint32_t l = 0; l < kSegLanes; l++) {
+            if (hipEventRecord(L->join[l], L->s[l]) != hipSuccess && !rc) rc = RADSORT_E_DEVICE;
+            if (hipStreamWaitEvent(s, L->join[l], 0) != hipSuccess && !rc) rc = RADSORT_E_DEVICE;
         }
     }
     g_stats.timed = 0;

@@ -69,6 +69,22 @@ def test_segments_match_oracle(kb, tuned):
     assert np.array_equal(dv.cpu().numpy().view(np.uint32).astype(np.uint64), ev)
 
 
+@pytest.mark.parametrize("kb", [4, 8])
+def test_segments_mixed_paths_match_oracle(kb):
+    """A table that keeps arrays up to 2^15 on the one-workgroup path and sends the
+    larger ones to the lanes (two classes there); the lanes run beside the batched
+    kernels."""
+    say(f"segments mixed paths kb={kb}")
+    sizes = list(workloads.log_uniform_sizes(0x5E8, 120, 10, 20)) + EDGE
+    offsets, keys, vals = batch(0x5E9 + kb, sizes, kb)
+    tuning = [(15, 0, 4), (18, 512, 8), (32, 2048, 11)]
+    dk, dv = to_dev(keys), to_dev(vals)
+    radsort.sort_segments_(dk, dv, offsets, tuning=tuning, check=True)
+    ek, ev = expected(offsets, keys, vals, kb)
+    assert np.array_equal(dk.cpu().numpy().view(NP[kb]).astype(np.uint64), ek)
+    assert np.array_equal(dv.cpu().numpy().view(np.uint32).astype(np.uint64), ev)
+
+
 def test_segments_keys_only_and_empty():
     sizes = [0, 5, 0, 9000, 1, 0]
     offsets, keys, _ = batch(11, sizes, 4)
