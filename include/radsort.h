@@ -24,6 +24,17 @@
  *   - return value: RADSORT_OK (0) or a negative RADSORT_E_* code.  Argument
  *     errors are detected before anything is enqueued and leave the data as it
  *     was.  After a device error the data is undefined.
+ *   - digit_bits is 1 .. 16 as an argument (sigma up to 2^16); widths 12 .. 16
+ *     return RADSORT_E_UNSUPPORTED from every call.  Three costs rule them out
+ *     on this GPU: (1) the 2 sigma head blocks of the state (Sec. 2.1) hold
+ *     2 sigma b elements, which stays within 1 % of n only for n >= 200 sigma b
+ *     (at 16 bits and b = 1024: 1.3e10 elements, above the 2^32 limit);
+ *     (2) a tile's per-wave digit counts take waves * sigma * 4 bytes of LDS
+ *     (at 16 bits: 1 MiB for 4 waves, beyond the 160 KiB of a compute unit);
+ *     (3) a tile holds 2048 to 8192 elements, so with sigma >= 2^12 a digit's
+ *     run in a tile averages two elements or fewer and the scatter writes
+ *     mostly partial 128-byte lines, costing more bytes than the round that the
+ *     wider digit saves (32-bit keys: 3 rounds at 11 bits, 2 at 16).
  */
 #ifndef RADSORT_H
 #define RADSORT_H
@@ -39,7 +50,7 @@ extern "C" {
 #define RADSORT_E_INVALID (-1)      /* bad argument: null pointer with n > 0, widths, b */
 #define RADSORT_E_NOMEM (-2)        /* allocation failed or workspace too small */
 #define RADSORT_E_DEVICE (-3)       /* a HIP call failed; see radsort_strerror */
-#define RADSORT_E_UNSUPPORTED (-4)  /* n >= 2^32 or digit_bits > 11 */
+#define RADSORT_E_UNSUPPORTED (-4)  /* n >= 2^32 or digit_bits 12 .. 16 */
 #define RADSORT_E_TIMEOUT (-5)      /* a device-side bounded wait gave up */
 
 /* flags of radsort_opts */
@@ -114,7 +125,7 @@ typedef struct radsort_stats {
  *   key_bytes      4 or 8 (uint32 / uint64 keys; signed or float keys are not
  *                  handled: the order is that of the unsigned bit patterns)
  *   payload_bytes  0 (payload must be NULL), 4 or 8
- *   digit_bits     1 .. 11
+ *   digit_bits     1 .. 11 (12 .. 16: RADSORT_E_UNSUPPORTED; 0 or > 16: INVALID)
  *   opts           may be NULL (b = 1024, library-allocated workspace)
  * Extra device memory is the workspace only: radsort_workspace_bytes().
  * n <= 1 returns RADSORT_OK without touching the data.

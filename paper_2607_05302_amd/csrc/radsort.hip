@@ -135,6 +135,8 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     if (key_bytes != 4 && key_bytes != 8) return RADSORT_E_INVALID;
     if (payload_bytes != 0 && payload_bytes != 4 && payload_bytes != 8) return RADSORT_E_INVALID;
     if (digit_bits < 1 || digit_bits > 16) return RADSORT_E_INVALID;
+    // 12 .. 16 bits: 2 sigma b head-block elements, waves * sigma LDS counts and
+    // digit runs shorter than a line per tile cost more than the round they save
     if (digit_bits > 11) return RADSORT_E_UNSUPPORTED;
     uint32_t b = (opts && opts->block_elems) ? opts->block_elems : 1024u;
     if (b < 64 || b > 65536 || (b & (b - 1))) return RADSORT_E_INVALID;

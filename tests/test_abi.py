@@ -67,6 +67,30 @@ def test_argument_errors(args, code):
     assert radsort.workspace_bytes(n, kb, vb, bits) == 0
 
 
+@pytest.mark.parametrize("bits", range(12, 17))
+@pytest.mark.parametrize("kb,vb", [(4, 0), (4, 4), (8, 8)])
+def test_wide_digits_are_unsupported(bits, kb, vb):
+    """digit_bits 12 .. 16 is a valid argument that every call refuses (the state's
+    2 sigma head blocks, the per-wave LDS counts and sub-line digit runs rule it
+    out); 17 is invalid."""
+    lib = radsort.load()
+    fake = ctypes.c_void_p(0x1000)
+    n = 1 << 20
+    pv = fake if vb else None
+    assert lib.radsort_sort_pairs(fake, pv, n, kb, vb, bits, None, None) == radsort.E_UNSUPPORTED
+    assert lib.radsort_oop_sort_pairs(fake, pv, n, kb, vb, bits, None, None) == radsort.E_UNSUPPORTED
+    assert lib.radsort_msd_sort_pairs(fake, pv, n, kb, vb, bits, None, None) == radsort.E_UNSUPPORTED
+    assert lib.radsort_sort_pairs_noalloc(fake, pv, n, kb, vb, bits, 1024, 0,
+                                          None) == radsort.E_UNSUPPORTED
+    st = ctypes.c_void_p()
+    assert lib.radsort_state_create(ctypes.byref(st), fake, pv, n, kb, vb, bits,
+                                    None) == radsort.E_UNSUPPORTED
+    assert not st.value
+    assert lib.radsort_histograms(fake, n, kb, bits, fake, None) == radsort.E_UNSUPPORTED
+    assert radsort.workspace_bytes(n, kb, vb, bits) == 0
+    assert lib.radsort_sort_pairs(fake, pv, n, kb, vb, 17, None, None) == radsort.E_INVALID
+
+
 @pytest.mark.parametrize("b", [32, 100, 1 << 17])
 def test_block_size_validation(b):
     lib = radsort.load()
