@@ -52,6 +52,8 @@ extern "C" {
 #define RADSORT_E_DEVICE (-3)       /* a HIP call failed; see radsort_strerror */
 #define RADSORT_E_UNSUPPORTED (-4)  /* n >= 2^32 or digit_bits 12 .. 16 */
 #define RADSORT_E_TIMEOUT (-5)      /* a device-side bounded wait gave up */
+#define RADSORT_E_ORDER (-6)        /* RADSORT_F_DEBUG_ORDER: a block was drawn before the
+                                       loads of its readers were marked returned */
 
 /* flags of radsort_opts */
 #define RADSORT_F_CHECK 1u          /* wait for the stream and report device-side errors */
@@ -72,6 +74,20 @@ extern "C" {
                                        the same P, f and logical contents, a different pi;
                                        faster.  Digits of more than 8 bits always draw in
                                        the sequential order */
+
+#define RADSORT_F_DEBUG_ORDER 16u   /* ordering check (the library built with RS_DEBUG_ORDER
+                                       defined; any other build returns
+                                       RADSORT_E_UNSUPPORTED): every Radsort round marks
+                                       each input block once the loads of the tile that
+                                       reads it have returned, and every draw of a block
+                                       holding input of the round checks the mark; a
+                                       missing mark sets error bit 4 (radsort_stats) and
+                                       the call returns RADSORT_E_ORDER.  Needs b <= the
+                                       round's tile (8192 elements for 4-byte keys);
+                                       slower; for tests.  With RADSORT_F_DEBUG_PLANT as
+                                       well the marks carry a wrong tag, so that every
+                                       checked draw reports (a test of the check) */
+#define RADSORT_F_DEBUG_PLANT 0x80000000u
 
 typedef struct radsort_opts {
     uint32_t block_elems;     /* b: block size in elements, a power of two in [64, 65536];

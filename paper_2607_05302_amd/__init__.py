@@ -20,8 +20,9 @@ import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libradsort.so")
 
-OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_TIMEOUT = 0, -1, -2, -3, -4, -5
-F_CHECK, F_TIMING, F_SHARED, F_SEQ_DRAWS = 1, 2, 4, 8
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_UNSUPPORTED, E_TIMEOUT, E_ORDER = 0, -1, -2, -3, -4, -5, -6
+F_CHECK, F_TIMING, F_SHARED, F_SEQ_DRAWS, F_DEBUG_ORDER = 1, 2, 4, 8, 16
+F_DEBUG_PLANT = 0x80000000  # with F_DEBUG_ORDER: marks with a wrong tag (tests the check)
 MAX_ROUNDS = 64
 
 # every function declared in include/radsort.h

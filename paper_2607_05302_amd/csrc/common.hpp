@@ -17,6 +17,7 @@ constexpr uint64_t kFlagInc = 2ull;
 // error bits written by kernels into the state's error word
 constexpr uint32_t kErrSpin = 1u;      // a bounded wait gave up
 constexpr uint32_t kErrBounds = 2u;    // an index left its range
+constexpr uint32_t kErrOrder = 4u;     // ordering-check builds: a block drawn before its loads returned
 
 // a wait gives up after this many polls (each poll sleeps ~64 cycles); correct
 // runs never come close, so a broken protocol ends the kernel instead of the GPU

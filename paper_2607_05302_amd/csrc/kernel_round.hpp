@@ -102,6 +102,9 @@ struct TileArgs {
     uint32_t shift, bits, log2b, npi, ring_log2;
     uint32_t st_log2;        // tiles per super-tile: 2^st_log2
     uint64_t* tl;            // timeline builds only: kTlStamps stamps per tile, or null
+    uint32_t* consumed;      // ordering-check builds only: per physical block, the tag of
+    uint32_t tag;            // the round whose loads of it returned last; or null
+    uint32_t tag_mark;       // the tag the marks carry (differs only to test the check)
 };
 
 // Timeline builds (RS_TIMELINE defined): thread 0 of each workgroup records the
@@ -424,6 +427,21 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     RS_STAMP(1);
+#ifdef RS_DEBUG_ORDER
+    // Ordering check: the tile's input blocks are marked as read (every load has
+    // returned), and the marks are released before the counts that allow the
+    // blocks' reuse.  Empty blocks (a bucket whose count is a multiple of b ends in
+    // one) are marked too: they hold nothing to read.  A block spans several tiles
+    // when b > E: checked only for b <= E.
+    if constexpr (!OOP) {
+        if (a.consumed && b <= (uint32_t)E) {
+            const uint32_t L = sigma + (uint32_t)(((uint64_t)tile * E) >> log2b) + tid;
+            if (tid < nblk && L < f_in) st_agent(a.consumed + bphys[tid], a.tag_mark);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+        }
+    }
+#endif
 
     // ---- per-digit tile counts (published at once) and wave offsets ------------------
     const uint32_t st0 = tile & ~(mst - 1);  // first tile of this tile's super-tile
@@ -713,6 +731,19 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
         }
         __syncthreads();
         RS_STAMP(11);
+#ifdef RS_DEBUG_ORDER
+        // Ordering check: every drawn block that holds input of this round (pool
+        // entry below f) must be marked read by its tile before the draw is
+        // published; the waits above (or the look-back, for this super-tile) ordered it.
+        if (a.consumed && b <= (uint32_t)E) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            for (uint32_t i = tid; i < nfills; i += NT) {
+                const uint32_t phys = pool[i];
+                if (sigma + F + i < f_in && phys < a.npi && ld_agent(a.consumed + phys) != a.tag)
+                    raise_error(a.err, kErrOrder);
+            }
+        }
+#endif
         if constexpr (SEQ) block_excl_scan<NT>(fpref, E / 32, tmp);
         // publish the tile's draws for every digit
         for (uint32_t d = tid; d < sigma; d += NT) {

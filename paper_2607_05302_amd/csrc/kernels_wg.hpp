@@ -33,13 +33,20 @@
 // partial blocks left to right in batches, then the blocks in T follow.  The
 // same two steps as the multi-kernel finalize, run by one workgroup.
 //
-// Wherever global memory that one thread stored is next loaded or stored by
-// another thread (the tail copy of setup and the first round; one round's
-// scatter and the next round; F1 and F2; one array and the next in the same T),
-// the workgroup passes a full hand-off (wg_global_handoff: release at agent
-// scope, barrier, acquire at agent scope).  A barrier alone waits for neither
-// stores nor loads, so where a thread loads what another thread overwrites after
-// a barrier (F2's batches), the loads are waited for before it.
+// Global memory between the threads (a CPU model of every load and store of
+// this kernel, with the thread that makes it, checks these rules):
+//  - a store that another thread next loads or stores is handed off
+//    (wg_global_handoff) between the two: the tail copy of setup before the
+//    first round's loads; one round's scatter before the next round's loads;
+//    F1's block moves (whole blocks, unused tails too) before F2's stores;
+//  - a load that another thread's later store overwrites has returned before
+//    the barrier between them: a tile's loads are used for its ranks and staging
+//    before the scatter's barrier; F2 waits for its batch before its barrier;
+//  - within a round no tile loads a block that this round wrote: the k-th draw
+//    takes input block k, and at most (elements so far) / b draws precede the
+//    end of a tile, so every drawn block lies in the drawing tile or before it.
+// A barrier alone waits for neither stores nor loads on gfx950 (no vmcnt wait
+// before s_barrier at workgroup scope).
 #pragma once
 
 #include "common.hpp"
@@ -102,7 +109,8 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
     __shared__ uint32_t Pidx[sigma], Plen[sigma], Pnidx[sigma], Pnlen[sigma];
     __shared__ uint32_t bphys[NBLK], blenT[NBLK];
     __shared__ uint32_t wfill[WAVES];
-    __shared__ uint32_t sh_arr, sh_f, sh_fout, sh_F, sh_tfill, sh_skip;
+    __shared__ uint32_t sh_arr, sh_f, sh_fout, sh_F, sh_tfill;
+    __shared__ uint32_t sh_skip[2];  // by round parity: see the round start
     __shared__ uint32_t visited[(kWgMaxBlocks + 31) / 32];
 
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -110,8 +118,11 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
     V* const Tv = (V*)((uint8_t*)Tk + (2ull * sigma << log2b) * KB);
 
     for (;;) {
-        // the previous array is done with LDS, and its stores to this workgroup's T
-        // have landed before the next array writes there
+        // the previous array is done with LDS, and a full hand-off.  By the rules
+        // below this one orders no global access (the previous array's last
+        // accesses to T are F1's stores, handed off before F2, and F2's loads,
+        // waited for), yet with a plain barrier here the batch sorted an array of
+        // 3 145 733 uint32 pairs wrong on its first run: it stays
         wg_global_handoff();
         if (tid == 0) sh_arr = atomicAdd(claim, 1u);
         __syncthreads();
@@ -189,13 +200,18 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
                 }
                 sh_fout = sigma + run;
                 sh_F = 0;
-                sh_skip = trivial;
+                sh_skip[r & 1] = trivial;
             }
             __syncthreads();
             // every element has the same digit at this position: the stable round
             // would leave the logical sequence as it is, so it is left out (the state
-            // of the previous round stays, which finalize takes as it is)
-            if (sh_skip) continue;
+            // of the previous round stays, which finalize takes as it is).  A thread
+            // that leaves the round out goes on to the next round start at once,
+            // where thread 0 writes the flag of round r + 1 while other threads may
+            // still read that of round r: hence one flag per round parity (thread 0
+            // reaches round r + 2 only after every thread has passed round r + 1's
+            // barrier, so after every read of round r's flag).
+            if (sh_skip[r & 1]) continue;
             const uint32_t f_in = sh_f;
             const uint32_t tiles = (((f_in - sigma) << log2b) + E - 1) / E;
             for (uint32_t tile = 0; tile < tiles; tile++) {

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -109,6 +110,7 @@ struct Geo {
 struct Layout {
     uint64_t Tk, Tv, pi0, pi1, blen, opened, S, Pidx, Plen, f, est, ctr, ring, agg, done,
         csum, stcnt, fin, alt_k, alt_v;
+    uint64_t consumed;  // ordering-check builds only: a tag per physical block
     uint64_t ring_bytes, fin_bytes, total;
 };
 
@@ -138,6 +140,9 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     // 12 .. 16 bits: 2 sigma b head-block elements, waves * sigma LDS counts and
     // digit runs shorter than a line per tile cost more than the round they save
     if (digit_bits > 11) return RADSORT_E_UNSUPPORTED;
+#ifndef RS_DEBUG_ORDER
+    if (opts && (opts->flags & RADSORT_F_DEBUG_ORDER)) return RADSORT_E_UNSUPPORTED;
+#endif
     uint32_t b = (opts && opts->block_elems) ? opts->block_elems : 1024u;
     if (b < 64 || b > 65536 || (b & (b - 1))) return RADSORT_E_INVALID;
     if (n >= (1ull << 32)) return RADSORT_E_UNSUPPORTED;
@@ -156,6 +161,9 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     g.npi = (uint32_t)npi;
     g.E = tile_elems(g.kb, g.vb, g.bits, false);
     g.oop_E = tile_elems(g.kb, g.vb, g.bits, true);
+#ifdef RS_DEBUG_ORDER
+    if (opts && (opts->flags & RADSORT_F_DEBUG_ORDER) && g.b > g.E) return RADSORT_E_UNSUPPORTED;
+#endif
     // input slots of a round: at most (floor(n/b) + sigma) blocks of b
     uint64_t slots = (g.nb + g.sigma) << g.log2b;
     g.tiles = (uint32_t)((slots + g.E - 1) / g.E);
@@ -210,6 +218,9 @@ Layout make_layout(const Geo& g, bool oop)
     L.f = take(4 * (nt + 1));
     L.est = take(4 * nt * sig);
     L.ctr = take(4 * (nt + 8));
+#ifdef RS_DEBUG_ORDER
+    L.consumed = oop ? 0 : take(4ull * g.npi);
+#endif
     // the look-back ring (count words, done words) and the chunk sums of the
     // super-tile scan, zeroed before each round; then the super-tile digit starts.
     // Finalize reuses all of it.
@@ -322,6 +333,9 @@ struct radsort_state {
     bool shared = false;       // other work shares the GPU: no cooperative launch at all
     bool seq_draws = false;    // draws in the sequential pool order (RADSORT_F_SEQ_DRAWS)
     int msd_shift = -1;        // >= 0: the rounds sort the digit at this shift (MSD split)
+    bool debug_order = false;  // ordering-check builds: RADSORT_F_DEBUG_ORDER
+    bool debug_plant = false;  // ... and RADSORT_F_DEBUG_PLANT: marks with a wrong tag
+    uint32_t debug_seq = 0;    // the state's number, part of the round tags
 
     uint32_t* u32(uint64_t off) const { return (uint32_t*)(ws + off); }
     uint32_t* pi(int which) const { return u32(which ? L.pi1 : L.pi0); }
@@ -581,6 +595,11 @@ template <int KB, int VB> struct Ops {
 #ifdef RS_TIMELINE
         a.tl = g.tiles <= g_tl_tiles ? g_tl : nullptr;
 #endif
+#ifdef RS_DEBUG_ORDER
+        a.consumed = st->debug_order ? st->u32(st->L.consumed) : nullptr;
+        a.tag = st->debug_seq << 8 | (r + 1);  // one per state and round
+        a.tag_mark = st->debug_plant ? a.tag ^ 0x80u : a.tag;
+#endif
         uint32_t* stcnt = (uint32_t*)(st->ws + st->L.stcnt);
         a.stbase = stcnt;
         // the ring is clear: setup or the previous round's fixup cleared it
@@ -795,7 +814,7 @@ int read_err(radsort_state* st, hipStream_t s, uint32_t* bits)
     RS_HIP(hipStreamSynchronize(s));
     if (bits) *bits = e;
     g_stats.error_bits = e;
-    return e ? RADSORT_E_TIMEOUT : RADSORT_OK;
+    return (e & kErrOrder) ? RADSORT_E_ORDER : e ? RADSORT_E_TIMEOUT : RADSORT_OK;
 }
 
 }  // namespace
@@ -1031,6 +1050,12 @@ int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_
     st->vals = payload;
     st->count = n;
     st->seq_draws = opts && (opts->flags & RADSORT_F_SEQ_DRAWS);
+#ifdef RS_DEBUG_ORDER
+    static std::atomic<uint32_t> debug_states{0};
+    st->debug_order = opts && (opts->flags & RADSORT_F_DEBUG_ORDER);
+    st->debug_plant = st->debug_order && (opts->flags & RADSORT_F_DEBUG_PLANT);
+    st->debug_seq = (debug_states.fetch_add(1) + 1) & 0xFFFFFFu;
+#endif
     if (opts && opts->workspace) {
         if (opts->workspace_bytes < st->L.total) {
             delete st;
@@ -1214,7 +1239,7 @@ int radsort_workspace_error(const void* workspace, uint64_t n, int key_bytes, in
                           hipMemcpyDeviceToHost, s));
     RS_HIP(hipStreamSynchronize(s));
     if (error_bits) *error_bits = e;
-    return e ? RADSORT_E_TIMEOUT : RADSORT_OK;
+    return (e & kErrOrder) ? RADSORT_E_ORDER : e ? RADSORT_E_TIMEOUT : RADSORT_OK;
 }
 
 int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes, int payload_bytes,
@@ -1372,6 +1397,7 @@ const char* radsort_strerror(int code)
     case RADSORT_E_DEVICE: return hipGetErrorString(g_last_hip);
     case RADSORT_E_UNSUPPORTED: return "unsupported size or digit width";
     case RADSORT_E_TIMEOUT: return "a device-side wait gave up (protocol error)";
+    case RADSORT_E_ORDER: return "ordering check: a block was drawn before its loads were marked";
     default: return "unknown error";
     }
 }

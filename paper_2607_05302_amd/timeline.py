@@ -47,9 +47,7 @@ STEP_END = {0: "start", 1: "load+rank", 2: "counts", 13: "(to stage)", 3: "stage
 
 def build_timeline() -> str:
     os.makedirs(TL_DIR, exist_ok=True)
-    cmd = [hipbuild.HIPCC, *hipbuild.FLAGS, "-DRS_TIMELINE", "-o", TL_LIB,
-           os.path.join(hipbuild.CSRC, "radsort.hip")]
-    subprocess.run(cmd, check=True)
+    subprocess.run(hipbuild._command(TL_LIB, ("RS_TIMELINE",)), check=True)
     return TL_LIB
 
 

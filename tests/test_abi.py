@@ -155,8 +155,29 @@ def test_trivial_sizes_are_no_ops():
 
 def test_strerror_texts():
     for code in (radsort.OK, radsort.E_INVALID, radsort.E_NOMEM, radsort.E_UNSUPPORTED,
-                 radsort.E_TIMEOUT):
+                 radsort.E_TIMEOUT, radsort.E_ORDER):
         assert radsort.strerror(code)
+    assert radsort.strerror(radsort.E_ORDER) != radsort.strerror(radsort.E_TIMEOUT)
+
+
+def test_ordering_check_only_in_its_build():
+    """RADSORT_F_DEBUG_ORDER is refused by the product library; the ordering-check
+    build exports the same symbols and refuses blocks larger than the tile."""
+    from paper_2607_05302_amd import build as hipbuild
+    fake = ctypes.c_void_p(0x1000)
+    o = radsort.Opts()
+    o.block_elems, o.flags = 1024, radsort.F_DEBUG_ORDER
+    lib = radsort.load()
+    assert lib.radsort_sort_pairs(fake, fake, 1 << 20, 4, 4, 8, ctypes.byref(o),
+                                  None) == radsort.E_UNSUPPORTED
+    dbg = radsort.load(hipbuild.DEBUG_ORDER_LIB)
+    for name in declared_functions():
+        assert hasattr(dbg, name), name
+    o.block_elems = 16384  # the tile of 4-byte keys and payload holds 8192 elements
+    assert dbg.radsort_sort_pairs(fake, fake, 1 << 20, 4, 4, 8, ctypes.byref(o),
+                                  None) == radsort.E_UNSUPPORTED
+    # without the flag the ordering-check build takes what the product build takes
+    assert dbg.radsort_workspace_bytes(1 << 20, 4, 4, 8, None) > 0
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
