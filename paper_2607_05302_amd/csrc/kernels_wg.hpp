@@ -12,7 +12,9 @@
 // workgroup owns one such T (its slot of the workspace).
 //
 // Per round, for each tile of E slots of the logical block sequence:
-//  1. load the tile (block table in LDS: physical block and used length);
+//  1. load the tile: each wave reads its slots of one block (physical block from
+//     pi, used length from P); the loads are issued during the previous tile,
+//     after its staging, so that they are in flight during its scatter;
 //  2. stable rank per wave by the OR table (as in the round kernel), then the
 //     tile's per-digit counts and each wave's offset within its digit;
 //  3. an element's rank in its bucket is base[d] + its tile rank; the elements
@@ -98,6 +100,7 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
     static_assert(E >= (int)b && (E & (E - 1)) == 0, "a tile holds whole blocks");
     static_assert(b % NT == 0, "threads split a block evenly");
     static_assert(NT == 512, "the launch bounds");
+    static_assert((int)b >= SEG, "a wave's slots lie in one block");
 
     __shared__ K sk[E];
     __shared__ V sv[VB ? E : 1];
@@ -107,7 +110,6 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
     __shared__ uint32_t hist[nt][sigma];
     __shared__ uint32_t S[sigma], base[sigma], tcnt[sigma], tdo[sigma];
     __shared__ uint32_t Pidx[sigma], Plen[sigma], Pnidx[sigma], Pnlen[sigma];
-    __shared__ uint32_t bphys[NBLK], blenT[NBLK];
     __shared__ uint32_t wfill[WAVES];
     __shared__ uint32_t sh_arr, sh_f, sh_fout, sh_F, sh_tfill;
     __shared__ uint32_t sh_skip[2];  // by round parity: see the round start
@@ -214,24 +216,42 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
             if (sh_skip[r & 1]) continue;
             const uint32_t f_in = sh_f;
             const uint32_t tiles = (((f_in - sigma) << log2b) + E - 1) / E;
-            for (uint32_t tile = 0; tile < tiles; tile++) {
-                // block table of the tile
-                if (tid < NBLK) {
-                    const uint32_t L = sigma + tile * NBLK + tid;
-                    uint32_t phys = 0, len = 0;
-                    if (L < f_in) {
-                        phys = pit[ci][L];
-                        len = b;
-                        for (uint32_t e = 0; e < sigma; e++)
-                            if (Pidx[e] == L) len = Plen[e];
-                        if (phys >= npi) {  // never for a consistent state
-                            raise_error(err, kErrBounds);
-                            len = 0;
-                        }
+            // The loads of a tile are issued during the previous tile (after its
+            // staging), so that they are in flight during its scatter.  No tile of a
+            // round writes a block that a later tile of the round reads (every drawn
+            // block lies in the drawing tile or before it), so the early loads see
+            // the round's input.  A wave's slots lie in one block (b >= E / waves).
+            K kn[ITEMS];
+            V vn[ITEMS];
+            bool vld[ITEMS];
+            auto issue = [&](uint32_t t) {
+                const uint32_t bi = (wave * SEG) >> log2b, off0 = (wave * SEG) & (b - 1);
+                const uint32_t L = sigma + t * NBLK + bi;
+                uint32_t phys = 0, len = 0;
+                if (t < tiles && L < f_in) {
+                    phys = pit[ci][L];
+                    len = b;
+                    for (uint32_t e = 0; e < sigma; e++)
+                        if (Pidx[e] == L) len = Plen[e];
+                    if (phys >= npi) {  // never for a consistent state
+                        if (lane == 0) raise_error(err, kErrBounds);
+                        phys = 0;
+                        len = 0;
                     }
-                    bphys[tid] = phys;
-                    blenT[tid] = len;
                 }
+                const K* kp = blockat(A, Tk, phys, two_sigma, log2b) + off0 + lane;
+                const V* vp = nullptr;
+                if constexpr (VB != 0) vp = blockat(Av, Tv, phys, two_sigma, log2b) + off0 + lane;
+#pragma unroll
+                for (int j = 0; j < ITEMS; j++) {
+                    const bool v = off0 + j * 64 + lane < len;
+                    vld[j] = v;
+                    kn[j] = v ? kp[j * 64] : (K)0;
+                    if constexpr (VB != 0) vn[j] = v ? vp[j * 64] : (V)0;
+                }
+            };
+            issue(0);
+            for (uint32_t tile = 0; tile < tiles; tile++) {
                 for (uint32_t i = lane; i < sigma; i += 64) {
                     ort[wave][i] = 0;
                     wh[wave][i] = 0;
@@ -242,13 +262,9 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
                 uint32_t rk[ITEMS];  // wave rank << 8 | digit, or ~0 for an empty slot
 #pragma unroll
                 for (int j = 0; j < ITEMS; j++) {
-                    const uint32_t s = wave * SEG + j * 64 + lane;
-                    const uint32_t bi = s >> log2b, off = s & (b - 1);
-                    const bool v = off < blenT[bi];
-                    key[j] = v ? blockat(A, Tk, bphys[bi], two_sigma, log2b)[off] : (K)0;
-                    if constexpr (VB != 0)
-                        val[j] = v ? blockat(Av, Tv, bphys[bi], two_sigma, log2b)[off] : (V)0;
-                    rk[j] = v ? 0u : ~0u;
+                    key[j] = kn[j];
+                    if constexpr (VB != 0) val[j] = vn[j];
+                    rk[j] = vld[j] ? 0u : ~0u;
                 }
                 // stable rank within the wave, slots in order (j, lane)
                 const uint64_t mybit = 1ull << lane;
@@ -329,6 +345,7 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
                     for (int w = 0; w < WAVES; w++) t += wfill[w];
                     sh_tfill = t;
                 }
+                issue(tile + 1);  // key and val are staged: the next tile's loads
                 __syncthreads();  // staged; every draw of the tile is in pi'
                 uint32_t total = 0;
                 for (uint32_t d = 0; d < sigma; d++) total += tcnt[d];

@@ -53,6 +53,15 @@ class Memory:
     def _between(self, arr, a, b):
         return arr[b] - arr[a] > 0
 
+    def consume(self, addr, th):
+        """A load issued earlier (consumed=False) is waited for here: from now on
+        it counts as returned before the next barrier."""
+        for i, (s, t, c) in enumerate(self.loads.get(addr, ())):
+            if t == th and not c:
+                self.loads[addr][i] = (self.seg, t, True)
+                return
+        raise AssertionError("no pending load")
+
     def load(self, addr, th, consumed=True):
         st = self.last_store.get(addr)
         if st is not None and st[1] != th:
@@ -148,26 +157,32 @@ def run_array(mem, keys, cfg, base_addr):
         F = 0
         pit2 = list(pit)  # pi'; entries not written this round are rewritten by fixup
         tiles = ((f - sigma) * b + E - 1) // E
-        for tile in range(tiles):
-            bphys, blen = [], []
+
+        def issue(t):
+            """The loads of tile t, issued early (during tile t - 1)."""
+            out = []
             for k in range(NBLK):
-                L = sigma + tile * NBLK + k
-                if L < f:
-                    ln = b
-                    for e in range(sigma):
-                        if Pidx[e] == L:
-                            ln = Plen[e]
-                    bphys.append(pit[L])
-                    blen.append(ln)
-                else:
-                    bphys.append(0)
-                    blen.append(0)
-            mem.sync("B")  # block table
+                L = sigma + t * NBLK + k
+                if t >= tiles or L >= f:
+                    continue
+                ln = b
+                for e in range(sigma):
+                    if Pidx[e] == L:
+                        ln = Plen[e]
+                for off in range(ln):
+                    s = k * b + off
+                    addr = blockat(pit[L], off)
+                    out.append((s, addr, slot_thread(s),
+                                mem.load(addr, slot_thread(s), consumed=False)))
+            return out
+
+        pending = issue(0)
+        for tile in range(tiles):
+            mem.sync("B")  # top of the tile: the previous tile is done with LDS
             elems = []  # (slot, key pair) in slot order
-            for s in range(E):
-                bi, off = divmod(s, b)
-                if off < blen[bi]:
-                    elems.append((s, mem.load(blockat(bphys[bi], off), slot_thread(s))))
+            for s, addr, th, kv in pending:
+                mem.consume(addr, th)
+                elems.append((s, kv))
             mem.sync("B")  # ranked
             mem.sync("B")  # tile counts
             cnt = [0] * sigma
@@ -196,6 +211,7 @@ def run_array(mem, keys, cfg, base_addr):
                 d = (kv[0] >> shift) & dmask
                 stage[tdo[d] + seen[d]] = kv
                 seen[d] += 1
+            pending = issue(tile + 1)
             mem.sync("B")  # staged, draws in pi'
             for p, kv in enumerate(stage):
                 d = (kv[0] >> shift) & dmask
