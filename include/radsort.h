@@ -106,7 +106,9 @@ typedef struct radsort_opts {
  * there; a smaller array (but above the whole-in-LDS limit of 8192, or 4096 for
  * records of 12 bytes or more) runs there when its class has block_elems > 0, and on
  * one workgroup of the batched kernel when block_elems = 0 or no class covers it.
- * digit_bits must be 4, 8 or 11 and block_elems 0 or a power of two in [64, 65536]. */
+ * digit_bits must be 4, 8 or 11 and block_elems 0 or a power of two in [64, 65536];
+ * a class with block_elems = 0 takes the batched kernel's own digits (5 bits, b =
+ * 1024) and its digit_bits is not used. */
 #define RADSORT_SEG_CLASSES 32
 typedef struct radsort_seg_tuning {
     uint32_t classes;
@@ -198,8 +200,8 @@ uint64_t radsort_oop_workspace_bytes(uint64_t n, int key_bytes, int payload_byte
  * are each sorted whole in LDS by one workgroup, with 8-bit digits and no
  * workspace.  Arrays of up to 4 423 680 elements are sorted by Radsort (Alg. 2:
  * setup, n_t x sortPhase + fixupPhase, finalize) run by one workgroup per array,
- * all of them in one launch, with 4-bit digits and b = 1024 (each of at most 256
- * workgroups owns a T of 2 * 16 * 1024 elements in the workspace).  Larger arrays
+ * all of them in one launch, with 5-bit digits and b = 1024 (each of at most 256
+ * workgroups owns a T of 2 * 32 * 1024 elements in the workspace).  Larger arrays
  * each run the Radsort steps with the block size and digit width of their size
  * class in `tuning` (NULL: b = 2^ceil(log2 sqrt n) in [64, 2048] and 8-bit digits,
  * after the b in Theta(sqrt n) of Sec. 3), in launch forms that need no

@@ -6,10 +6,14 @@
 // ring: it walks the tiles of a round in order, so the digit bases and the
 // block draws are running counts in LDS, exactly as in the sequential scan.
 //
-// Fixed shape: digits of kWgBits = 4 bits (sigma = 16) and blocks of
-// b = 2^kWgLog2b = 1024 elements, so that pi, pi' (n_pi <= kWgMaxBlocks words
-// each) live in LDS and T (2 sigma b elements per plane) is small; each
-// workgroup owns one such T (its slot of the workspace).
+// Fixed shape: digits of kWgBits = 5 bits (sigma = 32; 7 rounds for 32-bit keys,
+// 13 for 64-bit) and blocks of b = 2^kWgLog2b = 1024 elements, so that pi, pi'
+// (n_pi <= kWgMaxBlocks 16-bit entries each) live in LDS and T (2 sigma b =
+// 65536 elements per plane) is small; each workgroup owns one such T (its slot
+// of the workspace).  On a batch of 4096 arrays of up to 2^22 uint32 pairs this
+// took 137.4 ms, against 145.9 ms with 4-bit digits (b = 1024), 139.8 ms with
+// 6-bit digits (b = 1024, twice the workspace) and 174.6 ms with 6-bit digits
+// and b = 512 (twice the blocks: finalize and the block tables cost more).
 //
 // Per round, for each tile of E slots of the logical block sequence:
 //  1. load the tile: each wave reads its slots of one block (physical block from
@@ -55,10 +59,10 @@
 
 namespace rs {
 
-constexpr uint32_t kWgBits = 4;
+constexpr uint32_t kWgBits = 5;
 constexpr uint32_t kWgSigma = 1u << kWgBits;
 constexpr uint32_t kWgLog2b = 10;
-constexpr uint32_t kWgMaxBlocks = 4352;  // n_pi of the largest array the path takes
+constexpr uint32_t kWgMaxBlocks = 4384;  // n_pi of the largest array the path takes
 // blocks in flight per thread in finalize: 8, or 4 for records of 12 bytes or more
 template <int KB, int VB> constexpr uint32_t wg_depth() { return KB + VB >= 12 ? 4u : 8u; }
 
@@ -100,18 +104,21 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
     static_assert(E >= (int)b && (E & (E - 1)) == 0, "a tile holds whole blocks");
     static_assert(b % NT == 0, "threads split a block evenly");
     static_assert(NT == 512, "the launch bounds");
-    static_assert((int)b >= SEG, "a wave's slots lie in one block");
+    static_assert(SEG % (int)b == 0 || (int)b % SEG == 0, "waves and blocks nest");
+    static_assert(sigma <= 64, "one wave scans the digits");
+    static_assert(kWgMaxBlocks <= 65536, "pi entries are 16-bit");
+    constexpr uint32_t WB = SEG >= (int)b ? SEG / b : 1;  // blocks a wave reads
 
     __shared__ K sk[E];
     __shared__ V sv[VB ? E : 1];
-    __shared__ uint32_t pit[2][kWgMaxBlocks];  // pi and pi', swapped by index each round
+    __shared__ uint16_t pit[2][kWgMaxBlocks];  // pi and pi', swapped by index each round
     __shared__ uint64_t ort[WAVES][sigma];
     __shared__ uint32_t wh[WAVES][sigma];  // per-wave counts, then offsets within the tile
     __shared__ uint32_t hist[nt][sigma];
     __shared__ uint32_t S[sigma], base[sigma], tcnt[sigma], tdo[sigma];
     __shared__ uint32_t Pidx[sigma], Plen[sigma], Pnidx[sigma], Pnlen[sigma];
     __shared__ uint32_t wfill[WAVES];
-    __shared__ uint32_t sh_arr, sh_f, sh_fout, sh_F, sh_tfill;
+    __shared__ uint32_t sh_arr, sh_f, sh_fout, sh_F, sh_tfill, sh_total;
     __shared__ uint32_t sh_skip[2];  // by round parity: see the round start
     __shared__ uint32_t visited[(kWgMaxBlocks + 31) / 32];
 
@@ -169,7 +176,7 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
         // ---- setup (Alg. 4) ----------------------------------------------------------
         const uint32_t f0 = sigma + nb + 1;
         for (uint32_t L = tid; L < npi; L += NT)
-            pit[0][L] = L < sigma ? L : (L + 1 < f0 ? L + sigma : sigma + (L - (f0 - 1)));
+            pit[0][L] = (uint16_t)(L < sigma ? L : (L + 1 < f0 ? L + sigma : sigma + (L - (f0 - 1))));
         for (uint32_t i = tid; i < tail; i += NT) {
             Tk[((uint64_t)sigma << log2b) + i] = A[((uint64_t)nb << log2b) + i];
             if constexpr (VB != 0) Tv[((uint64_t)sigma << log2b) + i] = Av[((uint64_t)nb << log2b) + i];
@@ -224,30 +231,43 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
             K kn[ITEMS];
             V vn[ITEMS];
             bool vld[ITEMS];
+            // used length of logical block L: b, or that of the partial block of P
+            // (P's entries ascend: one binary search)
+            auto block_len = [&](uint32_t L) {
+                uint32_t lo = 0, hi = sigma;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (Pidx[mid] < L) lo = mid + 1;
+                    else hi = mid;
+                }
+                return lo < sigma && Pidx[lo] == L ? Plen[lo] : b;
+            };
             auto issue = [&](uint32_t t) {
-                const uint32_t bi = (wave * SEG) >> log2b, off0 = (wave * SEG) & (b - 1);
-                const uint32_t L = sigma + t * NBLK + bi;
-                uint32_t phys = 0, len = 0;
-                if (t < tiles && L < f_in) {
-                    phys = pit[ci][L];
-                    len = b;
-                    for (uint32_t e = 0; e < sigma; e++)
-                        if (Pidx[e] == L) len = Plen[e];
-                    if (phys >= npi) {  // never for a consistent state
-                        if (lane == 0) raise_error(err, kErrBounds);
-                        phys = 0;
-                        len = 0;
+                uint32_t phys[WB], len[WB];
+#pragma unroll
+                for (uint32_t w = 0; w < WB; w++) {
+                    const uint32_t L = sigma + t * NBLK + ((wave * SEG) >> log2b) + w;
+                    phys[w] = 0;
+                    len[w] = 0;
+                    if (t < tiles && L < f_in) {
+                        phys[w] = pit[ci][L];
+                        len[w] = block_len(L);
+                        if (phys[w] >= npi) {  // never for a consistent state
+                            if (lane == 0) raise_error(err, kErrBounds);
+                            phys[w] = 0;
+                            len[w] = 0;
+                        }
                     }
                 }
-                const K* kp = blockat(A, Tk, phys, two_sigma, log2b) + off0 + lane;
-                const V* vp = nullptr;
-                if constexpr (VB != 0) vp = blockat(Av, Tv, phys, two_sigma, log2b) + off0 + lane;
 #pragma unroll
                 for (int j = 0; j < ITEMS; j++) {
-                    const bool v = off0 + j * 64 + lane < len;
+                    const uint32_t w = SEG >= (int)b ? ((uint32_t)j * 64) >> log2b : 0u;
+                    const uint32_t off = ((wave * SEG + (uint32_t)j * 64) & (b - 1)) + lane;
+                    const bool v = off < len[w];
                     vld[j] = v;
-                    kn[j] = v ? kp[j * 64] : (K)0;
-                    if constexpr (VB != 0) vn[j] = v ? vp[j * 64] : (V)0;
+                    kn[j] = v ? blockat(A, Tk, phys[w], two_sigma, log2b)[off] : (K)0;
+                    if constexpr (VB != 0)
+                        vn[j] = v ? blockat(Av, Tv, phys[w], two_sigma, log2b)[off] : (V)0;
                 }
             };
             issue(0);
@@ -295,12 +315,11 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
                     tcnt[tid] = run;
                 }
                 __syncthreads();
-                if (tid == 0) {
-                    uint32_t run = 0;
-                    for (uint32_t d = 0; d < sigma; d++) {
-                        tdo[d] = run;
-                        run += tcnt[d];
-                    }
+                if (wave == 0) {  // the tile's staging start of each digit
+                    const uint32_t c = lane < sigma ? tcnt[lane] : 0u;
+                    const uint32_t incl = wave_incl_scan(c);
+                    if (lane < sigma) tdo[lane] = incl - c;
+                    if (lane == 63) sh_total = incl;
                 }
                 // the elements that fill a block draw, in slot order
                 auto fills_block = [&](int j) {
@@ -347,8 +366,7 @@ __global__ __launch_bounds__(512) void k_radsort_wg(
                 }
                 issue(tile + 1);  // key and val are staged: the next tile's loads
                 __syncthreads();  // staged; every draw of the tile is in pi'
-                uint32_t total = 0;
-                for (uint32_t d = 0; d < sigma; d++) total += tcnt[d];
+                const uint32_t total = sh_total;
                 for (uint32_t p = tid; p < total; p += NT) {
                     const K k = sk[p];
                     const uint32_t d = (uint32_t)(k >> shift) & dmask;

@@ -5,7 +5,7 @@ Arrays of up to 8192 elements (4096 for records of 12 bytes or more) are sorted
 whole in LDS and take no tuning.  For each larger class (arrays of up to 2^k
 elements, k = lo .. hi) the tuner times a batch with every candidate for that
 class and keeps the fastest: the one-workgroup path (one workgroup per array,
-4-bit digits, b = 1024; written as b = 0) for classes it can take (up to 4 423 680
+5-bit digits, b = 1024; written as b = 0) for classes it can take (up to 4 423 680
 elements), and the Radsort steps on the multi-workgroup lanes with b in
 {256 .. 8192} and digit bits in {4, 8, 11}.  The earlier classes keep their
 choices.  Classes the one-workgroup path can take are timed in a mixed batch of

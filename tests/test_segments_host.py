@@ -4,11 +4,11 @@ import numpy as np
 import paper_2607_05302_amd as radsort
 
 
-# the one-workgroup path: arrays of 8193 .. (4352 - 32) * 1024 elements (4-bit
-# digits, b = 1024); each of its workgroups owns T = 2 * 16 * 1024 elements (keys
+# the one-workgroup path: arrays of 8193 .. (4384 - 64) * 1024 elements (5-bit
+# digits, b = 1024); each of its workgroups owns T = 2 * 32 * 1024 elements (keys
 # and payload)
-WG_MAX = (4352 - 32) * 1024
-WG_SLOT = 2 * 16 * 1024 * (4 + 4)
+WG_MAX = (4384 - 64) * 1024
+WG_SLOT = 2 * 32 * 1024 * (4 + 4)
 
 
 def test_workspace_covers_only_the_large_arrays():
