@@ -18,7 +18,6 @@ throughput on the same input, and the CPU oracle timed on a sample.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -26,19 +25,11 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+from paper_2607_05302_amd.counters import kernel_sha  # noqa: E402  (source hash)
 
 METRIC = "keys/s & HBM GB/s, uint32 n=2^28, vs out-of-place LSD; peak extra bytes"
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_round_traffic.json")
-KERNEL_SOURCES = ["paper_2607_05302_amd/csrc/kernel_round.hpp",
-                  "paper_2607_05302_amd/csrc/common.hpp"]
-
-
-def kernel_sha() -> str:
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
-    return h.hexdigest()[:16]
 
 
 def log(*a):
