@@ -899,7 +899,11 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
     const bool wide = b >= 64 && (((uintptr_t)a.Ak | (uintptr_t)a.Av | (uintptr_t)a.Tk |
                                    (uintptr_t)a.Tv | (uintptr_t)f.temps) & 15) == 0;
     const uint64_t head_bytes = (uint64_t)b * (KB + VB);
-    const uint32_t jpw = (uint32_t)std::min<uint64_t>(8, kFinLdsBytes / (2 * head_bytes));
+    // jobs per workgroup: up to 8 (as the LDS allows), fewer for small states so that
+    // their jobs of 16 nodes still spread over lds_grid workgroups
+    const uint64_t jpw_fill = lds_grid ? (npi + 16ull * lds_grid - 1) / (16ull * lds_grid) : 1;
+    const uint32_t jpw = (uint32_t)std::min<uint64_t>(
+        std::min<uint64_t>(8, kFinLdsBytes / (2 * head_bytes)), std::max<uint64_t>(1, jpw_fill));
     if (lds_grid && jpw > 0) {
         // the cooperative form: jobs of at most kFinLdsJobMax nodes, jpw per workgroup
         uint32_t job = (uint32_t)((npi + (uint64_t)lds_grid * jpw - 1) / ((uint64_t)lds_grid * jpw));

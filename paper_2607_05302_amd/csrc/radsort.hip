@@ -55,11 +55,6 @@ int ilog2(uint64_t x)
     return r;
 }
 
-// Tile shape per record size and digit width: E = 64 * WAVES * ITEMS slots per
-// workgroup.  Bigger tiles mean fewer look-back steps and block requests per
-// element; the staged tile and the per-wave digit counts must fit in LDS (one
-// workgroup of up to 110 KB per CU), and the next tile's records, held in
-// registers while the current one is processed, must fit the register file.
 // Shape of the round kernel's workgroup per record size (KB key bytes, VB payload
 // bytes), digit width (WIDE: more than 8 bits) and round (OOP: Alg. 1).  E = 64 *
 // WAVES * ITEMS slots per tile.  The shape decides how many workgroups share a
