@@ -202,3 +202,15 @@ def test_noalloc_refusals_need_no_device():
     assert lib.radsort_sort_pairs_noalloc(fake, fake, 1000, 3, 4, 8, 1024, 0, None) == \
         radsort.E_INVALID
     assert lib.radsort_sort_pairs_noalloc(None, None, 0, 4, 0, 8, 0, 0, None) == radsort.OK
+
+
+def test_copy_argument_errors():
+    """radsort_copy refuses null and unaligned pointers before anything is enqueued,
+    and a copy of 0 bytes is a no-op that needs no device."""
+    lib = radsort.load()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.radsort_copy(None, fake, 16, None) == radsort.E_INVALID
+    assert lib.radsort_copy(fake, None, 16, None) == radsort.E_INVALID
+    assert lib.radsort_copy(ctypes.c_void_p(0x1004), fake, 16, None) == radsort.E_INVALID
+    assert lib.radsort_copy(fake, ctypes.c_void_p(0x1008), 16, None) == radsort.E_INVALID
+    assert lib.radsort_copy(None, None, 0, None) == radsort.OK
