@@ -120,7 +120,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--block", type=int, default=2048)
+    ap.add_argument("--block", type=int, default=None,
+                    help="block size b (default 2048; 4096 for the structured inputs)")
     ap.add_argument("--no-oop", action="store_true", help="skip the out-of-place baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -166,7 +167,7 @@ def main():
     if args.workload == "msd":
         return bench_msd(args)
     n = 1 << args.log2n
-    b, bits, kb, vb = args.block, 8, 4, 4
+    b, bits, kb, vb = args.block or 2048, 8, 4, 4
     seed = workloads.SEED_SMALL if args.log2n == 20 else workloads.SEED_LARGE
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -491,7 +492,7 @@ def resort_multiplier(step: int) -> int:
     return m - (1 << 32) if m >= 1 << 31 else m
 
 
-STRUCT_METRIC = "keys/s, uint64 keys only, n=2^30, 8-bit digits (8 rounds), b=1024: " \
+STRUCT_METRIC = "keys/s, uint64 keys only, n=2^30, 8-bit digits (8 rounds): " \
                 "Zipf(1.1) over 2^16 values, all equal, sorted, low 20 bits random"
 
 
@@ -510,7 +511,7 @@ def bench_structured(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log2n = 30 if args.log2n == 28 else args.log2n
-    n, b, bits = 1 << log2n, 1024, 8
+    n, b, bits = 1 << log2n, args.block or 4096, 8
     ws = torch.empty(radsort.workspace_bytes(n, 8, 0, bits, b), dtype=torch.uint8, device=dev)
     keys = torch.empty(n, dtype=torch.int64, device=dev)
     steps = max(1, min(args.steps, 3))
@@ -586,7 +587,7 @@ def bench_msd(args):
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    n, b, bits = 1 << args.log2n, args.block, 8
+    n, b, bits = 1 << args.log2n, args.block or 2048, 8
     keys0 = workloads.uniform_t(workloads.SEED_LARGE, n, 4, dev)
     vals0 = torch.arange(n, dtype=torch.int32, device=dev)
     keys, vals = torch.empty_like(keys0), torch.empty_like(vals0)
@@ -653,7 +654,7 @@ def bench_resort(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     n = 1 << args.log2n
-    b, bits, kb, vb = args.block, 8, 4, 4
+    b, bits, kb, vb = args.block or 2048, 8, 4, 4
     nt = 4
     keys = workloads.uniform_t(RESORT_SEED, n, 4, dev)
     vals = torch.arange(n, dtype=torch.int32, device=dev)
