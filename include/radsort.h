@@ -237,8 +237,11 @@ uint64_t radsort_segments_workspace_bytes(const uint64_t* offsets, uint32_t nseg
 int radsort_histograms(const void* keys, uint64_t n, int key_bytes, int digit_bits,
                        uint32_t* counts, void* stream);
 
-/* Statistics of the last sort call of this process.  If that call asked for
- * RADSORT_F_TIMING, this waits for its last event first. */
+/* Statistics of the last sort call made by the calling host thread (each thread
+ * keeps its own record; calls that one thread makes on several streams overwrite
+ * it, and each call's device-side error word stays readable per workspace through
+ * radsort_workspace_error).  If that call asked for RADSORT_F_TIMING, this waits
+ * for its last event first. */
 int radsort_last_stats(radsort_stats* out);
 
 /* Text for a return code (and, after RADSORT_E_DEVICE, the HIP error). */

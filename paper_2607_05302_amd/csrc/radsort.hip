@@ -32,7 +32,8 @@ thread_local hipError_t g_last_hip = hipSuccess;
 uint64_t* g_tl = nullptr;  // stamps of the Radsort round kernel (timeline builds)
 uint64_t g_tl_tiles = 0;
 #endif
-radsort_stats g_stats{};
+// statistics and phase events of the last sort call, per host thread
+thread_local radsort_stats g_stats{};
 
 #define RS_HIP(call)                                 \
     do {                                             \
@@ -301,7 +302,7 @@ struct Timer {
     }
 };
 
-Timer g_timer;
+thread_local Timer g_timer;
 
 void launch_fill(uint32_t* p, uint64_t count, uint32_t v, hipStream_t s)
 {
