@@ -293,83 +293,115 @@ void orc_round(orc_state *st, uint64_t t)
     st->counters[ORC_C_ROUNDS]++;
 }
 
-/* ---- swap and finalize (Alg. 7, readings G2 and G3) ------------------------------ */
+/* ---- finalize (Alg. 7, readings G2, G3 and G14) ----------------------------------
+ *
+ * The sorted sequence is the used part of logical blocks sigma .. f-1, in logical
+ * order.  It is packed into A from the front; `placed` counts the elements already
+ * there.  The walk gives each of the first floor(n/b) logical blocks L, for keeps,
+ * the physical block L + sigma (block L - sigma of A, reading G2) and appends L's
+ * elements at A[placed ..].  That range ends inside L's new block, so the only live
+ * data it can hit is what that block held: if the block holds a block of the
+ * sequence the walk has not reached, that block is first copied to a spare block
+ * (one that holds no live data) and re-bound there.  After the append, the block L
+ * came from holds nothing live and becomes the spare (reading G3).  The blocks past
+ * the first floor(n/b) then all sit in T, or, after a truncate, also right behind
+ * the homes (reading G14), and are appended in order.  pi and its inverse follow
+ * every move, so the state stays the permuted representation of the data. */
 
-/* Re-bind logical index i to physical block j in both pi and its inverse. */
+typedef struct {
+    uint64_t logical, phys;  /* a physical block without live data, and its binding */
+} orc_spare;
+
+/* Binds logical block i to physical block j in pi and in its inverse. */
 static void bind(orc_state *st, uint64_t i, uint64_t j)
 {
     st->pi[i] = j;
     st->pinv[j] = i;
 }
 
+/* Physical block `home` holds a block of the sequence that is still to come: copy it
+ * to the spare and exchange the two bindings.  Returns the logical index now bound
+ * to `home`, which holds nothing live. */
+static uint64_t evacuate(orc_state *st, uint64_t home, const orc_spare *spare)
+{
+    const uint64_t later = st->pinv[home];
+    memcpy(blockat(st, spare->phys), blockat(st, home), st->b * sizeof(orc_elem));
+    st->counters[ORC_C_FINALIZE_COPIES]++;
+    bind(st, later, spare->phys);
+    bind(st, spare->logical, home);
+    return spare->logical;
+}
+
+/* Appends the used elements of logical block L, held by physical block `from`, to the
+ * packed prefix of A.  Returns 0 when the lengths add up to more than n (a broken
+ * state: nothing more is moved). */
+static int append(orc_state *st, uint64_t L, uint64_t from, uint64_t *placed, uint64_t *iP)
+{
+    const uint64_t len = size_of_next_block(st, L, iP);
+    if (*placed + len > st->n) {
+        st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
+        return 0;
+    }
+    memmove(st->A + *placed, blockat(st, from), len * sizeof(orc_elem));
+    st->counters[ORC_C_FINALIZE_COPIES]++;
+    *placed += len;
+    return 1;
+}
+
+/* Reading G14: after a truncate A has more blocks than the floor(n/b) homes, and the
+ * physical block right behind the homes may hold a block of the remaining sequence,
+ * which the appends of the earlier remaining blocks would overwrite before it is
+ * read.  It moves to a block of T without live data (T holds at most sigma blocks of
+ * the sequence at this point, so one is free). */
+static void clear_behind_homes(orc_state *st, uint64_t homes)
+{
+    const uint64_t sigma = st->sigma, behind = 2 * sigma + homes;
+    if (behind >= st->npi) return;
+    const uint64_t occupant = st->pinv[behind];
+    if (occupant < sigma + homes || occupant >= st->f) return;
+    uint64_t t = 0;
+    while (t < 2 * sigma && st->pinv[t] >= sigma && st->pinv[t] < st->f) t++;
+    if (t == 2 * sigma) {
+        st->counters[ORC_C_FINALIZE_TAIL_OVERWRITTEN]++;
+        return;
+    }
+    const uint64_t idle = st->pinv[t];
+    memcpy(blockat(st, t), blockat(st, behind), st->b * sizeof(orc_elem));
+    st->counters[ORC_C_FINALIZE_COPIES]++;
+    bind(st, occupant, t);
+    bind(st, idle, behind);
+}
+
 void orc_finalize(orc_state *st)
 {
-    uint64_t sigma = st->sigma, b = st->b, nb = st->n / st->b, k = 0, iP = 0;
-    uint64_t i_free = 0, j_free = st->pi[0];
+    const uint64_t sigma = st->sigma, homes = st->n / st->b;
+    uint64_t placed = 0, iP = 0;
+    orc_spare spare = {0, st->pi[0]};  /* logical block 0 is unallocated (Sec. 2.2) */
     for (uint64_t i = 0; i < st->npi; i++) st->pinv[st->pi[i]] = i;
-    for (uint64_t i_in = sigma; i_in < sigma + nb; i_in++) {
-        uint64_t j_in = st->pi[i_in];
-        uint64_t j_out = i_in + sigma;              /* G2: home of logical i_in */
-        uint64_t i_out = st->pinv[j_out];
-        if (sigma <= i_out && i_out < i_in) st->counters[ORC_C_FINALIZE_HOME_TAKEN]++;
-        if (i_in < i_out && i_out < st->f) {
-            /* another allocated block still to be pulled sits at the home: push it */
-            memcpy(blockat(st, j_free), blockat(st, j_out), b * sizeof(orc_elem));
-            st->counters[ORC_C_FINALIZE_COPIES]++;
-            bind(st, i_out, j_free);                /* swap(i_out, j_out, i_free, j_free) */
-            bind(st, i_free, j_out);
-            i_out = i_free;                         /* G3: the pair (i_out, j_out) */
-        }
-        uint64_t l = size_of_next_block(st, i_in, &iP);
-        if (k + l > st->n) {  /* the lengths add up to more than n: a broken state */
-            st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
-            return;
-        }
-        memmove(st->A + k, blockat(st, j_in), l * sizeof(orc_elem));   /* pull */
-        st->counters[ORC_C_FINALIZE_COPIES]++;
-        k += l;
-        bind(st, i_in, j_out);                      /* swap(i_out, j_out, i_in, j_in) */
-        bind(st, i_out, j_in);
-        if (j_in != j_out) {                        /* G3: the block pulled from is free */
-            i_free = i_out;
-            j_free = j_in;
+    for (uint64_t L = sigma; L < sigma + homes; L++) {
+        const uint64_t home = L + sigma, from = st->pi[L];
+        uint64_t bound_there = st->pinv[home];
+        /* a block the walk has already placed can never sit at a later home */
+        if (bound_there >= sigma && bound_there < L) st->counters[ORC_C_FINALIZE_HOME_TAKEN]++;
+        if (bound_there > L && bound_there < st->f) bound_there = evacuate(st, home, &spare);
+        if (!append(st, L, from, &placed, &iP)) return;
+        /* L keeps `home`; the index bound there takes L's old block, now without live data */
+        bind(st, L, home);
+        bind(st, bound_there, from);
+        if (from != home) {
+            spare.logical = bound_there;
+            spare.phys = from;
         }
     }
-    /* G14: after truncate (Alg. 8) A has more blocks than the floor(n/b) homes, and
-     * the block right after the homes may hold a block of the tail, which the tail
-     * copies below would overwrite before reading it.  Move it to a free block of T
-     * first (T holds at most sigma allocated blocks at this point, so one is free). */
-    if (2 * sigma + nb < st->npi) {
-        uint64_t j_s = 2 * sigma + nb, i_s = st->pinv[j_s];
-        if (sigma + nb <= i_s && i_s < st->f) {
-            uint64_t j_t = 0;
-            while (j_t < 2 * sigma && st->pinv[j_t] >= sigma && st->pinv[j_t] < st->f) j_t++;
-            if (j_t == 2 * sigma) {
-                st->counters[ORC_C_FINALIZE_TAIL_OVERWRITTEN]++;
-            } else {
-                uint64_t i_t = st->pinv[j_t];
-                memcpy(blockat(st, j_t), blockat(st, j_s), b * sizeof(orc_elem));
-                st->counters[ORC_C_FINALIZE_COPIES]++;
-                bind(st, i_s, j_t);
-                bind(st, i_t, j_s);
-            }
-        }
-    }
-    for (uint64_t i_in = sigma + nb; i_in < st->f; i_in++) {
-        uint64_t j_in = st->pi[i_in];
-        /* the copies below write A[k .. n); a source in A must lie past that range */
-        if (j_in >= 2 * sigma && j_in - 2 * sigma <= nb)
+    clear_behind_homes(st, homes);
+    for (uint64_t L = sigma + homes; L < st->f; L++) {
+        const uint64_t from = st->pi[L];
+        /* the appends write A[placed .. n); a block of A they read must lie past that */
+        if (from >= 2 * sigma && from - 2 * sigma <= homes)
             st->counters[ORC_C_FINALIZE_TAIL_OVERWRITTEN]++;
-        uint64_t l = size_of_next_block(st, i_in, &iP);
-        if (k + l > st->n) {
-            st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
-            return;
-        }
-        memmove(st->A + k, blockat(st, j_in), l * sizeof(orc_elem));
-        st->counters[ORC_C_FINALIZE_COPIES]++;
-        k += l;
+        if (!append(st, L, from, &placed, &iP)) return;
     }
-    if (k != st->n) st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
+    if (placed != st->n) st->counters[ORC_C_FINALIZE_COUNT_MISMATCH]++;
 }
 
 /* ---- truncate (Alg. 8) and writing through the permuted representation (Sec. 4.1) -- */

@@ -25,8 +25,8 @@ SRC = os.path.join(ROOT, "oracle", "radsort_oracle.c")
 
 MUTANTS = {
     "alg3_literal_pi_compare": ("st->Pi[*iP] == i)", "st->Pi[*iP] == st->pi[i])"),
-    "alg7_literal_home_minus_sigma": ("uint64_t j_out = i_in + sigma;",
-                                      "uint64_t j_out = i_in - sigma;"),
+    "alg7_literal_home_minus_sigma": ("const uint64_t home = L + sigma, from",
+                                      "const uint64_t home = L - sigma, from"),
     "block_full_off_by_one": ("if (st->cur_fill[c] < b) continue;",
                               "if (st->cur_fill[c] < b - 1) continue;"),
     "msd_first_round_order": ("for (uint64_t t = nt; t-- > 0;) orc_round(st, t);",
@@ -43,9 +43,9 @@ MUTANTS = {
                             "st->pi2[L] = st->pi[L - 1]; /* unallocated */"),
     "setup_tail_wrong_offset": ("memcpy(blockat(st, sigma), st->A + b * (n / b),",
                                 "memcpy(blockat(st, sigma), st->A + b * (n / b) - 1,"),
-    "no_push_before_pull": ("if (i_in < i_out && i_out < st->f) {",
-                            "if (0 && i_in < i_out && i_out < st->f) {"),
-    "free_slot_not_updated": ("i_free = i_out;\n            j_free = j_in;",
+    "no_push_before_pull": ("if (bound_there > L && bound_there < st->f) bound_there =",
+                            "if (0 && bound_there > L) bound_there ="),
+    "free_slot_not_updated": ("spare.logical = bound_there;\n            spare.phys = from;",
                               "(void)0;"),
     "digit_from_low_end": ("uint64_t below = nt - 1 - t;", "uint64_t below = t;"),
     "truncate_keeps_f": ("st->f = i + 1;                                  /* block i is",
@@ -53,8 +53,8 @@ MUTANTS = {
     "truncate_length_off_by_one": ("st->Pl[e] = (uint64_t)(j + 1);",
                                    "st->Pl[e] = (uint64_t)(j + 2);"),
     "truncate_entry_after_block": ("if (i <= st->Pi[e]) {", "if (i < st->Pi[e]) {"),
-    "finalize_no_tail_relocation": ("if (2 * sigma + nb < st->npi) {",
-                                    "if (0 && 2 * sigma + nb < st->npi) {"),
+    "finalize_no_tail_relocation": ("    clear_behind_homes(st, homes);\n",
+                                    "    (void)clear_behind_homes;\n"),
     # the invariant checker itself
     "checker_always_fine": ("int orc_check_invariant(orc_state *st)\n{",
                             "int orc_check_invariant(orc_state *st)\n{\n    return 0;"),
