@@ -546,7 +546,7 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
 // global memory: jpw * 2 heads of b (s_k + s_v) bytes must fit the dynamic LDS.
 constexpr uint32_t kFinLdsThreads = 512;
 constexpr uint32_t kFinLdsBytes = 128u << 10;  // dynamic LDS for saved heads
-constexpr uint32_t kFinLdsJobMax = 1024;       // nodes per job held in LDS
+constexpr uint32_t kFinLdsJobMax = 4096;       // nodes per job held in LDS
 
 template <int KB, int VB, int VEC>
 __global__ __launch_bounds__(kFinLdsThreads) void k_fin_move_lds(
@@ -904,11 +904,19 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
     const uint64_t jpw_fill = lds_grid ? (npi + 16ull * lds_grid - 1) / (16ull * lds_grid) : 1;
     const uint32_t jpw = (uint32_t)std::min<uint64_t>(
         std::min<uint64_t>(8, kFinLdsBytes / (2 * head_bytes)), std::max<uint64_t>(1, jpw_fill));
+    // the cooperative form: jobs of at most kFinLdsJobMax nodes, jpw per workgroup;
+    // it must cover every node (at most n_pi of them), else the two-kernel form runs
+    uint32_t job = 0, cgrid = 0;
+    bool coop = false;
     if (lds_grid && jpw > 0) {
-        // the cooperative form: jobs of at most kFinLdsJobMax nodes, jpw per workgroup
-        uint32_t job = (uint32_t)((npi + (uint64_t)lds_grid * jpw - 1) / ((uint64_t)lds_grid * jpw));
+        job = (uint32_t)((npi + (uint64_t)lds_grid * jpw - 1) / ((uint64_t)lds_grid * jpw));
         job = std::max<uint32_t>(16, std::min<uint32_t>(job, kFinLdsJobMax));
-        const uint32_t grid = std::min<uint32_t>(lds_grid, (npi + job * jpw - 1) / (job * jpw));
+        cgrid = (uint32_t)std::min<uint64_t>(lds_grid, (npi + (uint64_t)job * jpw - 1) /
+                                                           ((uint64_t)job * jpw));
+        coop = (uint64_t)cgrid * jpw * job >= npi;
+    }
+    if (coop) {
+        const uint32_t grid = cgrid;
         const uint32_t lds = (uint32_t)(2 * jpw * head_bytes);
         void* args[] = {(void*)&a, (void*)&f, (void*)&rank, (void*)&clen, (void*)&M_ptr,
                         (void*)&job, (void*)&jpw};
