@@ -32,6 +32,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_round_traffic.json")
 
 
+
+def carries_keys(keys0, v, k, n):
+    """True when every index in v lies in [0, n) and keys0 at it (as unsigned 32-bit)
+    equals k; indices are checked before any gather with them."""
+    import torch
+    if not bool(((v >= 0) & (v < n)).all()):
+        return False
+    return bool(((keys0.to(torch.int64) & 0xFFFFFFFF)[v] == k).all())
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -216,7 +225,7 @@ def main():
     ok = bool((k[1:] >= k[:-1]).all())
     eq = k[1:] == k[:-1]
     ok &= bool((v[1:][eq] > v[:-1][eq]).all())
-    ok &= bool(((keys0.to(torch.int64) & 0xFFFFFFFF)[v] == k).all())
+    ok &= carries_keys(keys0, v, k, n)
     ok &= bool((torch.bincount(v, minlength=n) == 1).all())
     del k, v, eq
     if not ok:
@@ -394,11 +403,14 @@ def bench_segments(args):
     seg = torch.repeat_interleave(torch.arange(len(sizes), device=dev),
                                   torch.from_numpy(sizes).to(dev))
     ok &= bool((torch.searchsorted(off_dev[1:], v, right=True) == seg).all())
-    ok &= bool(((keys0.to(torch.int64) & 0xFFFFFFFF)[v] == k).all())
-    seen = torch.zeros(total, dtype=torch.bool, device=dev)
-    seen[v] = True
-    ok &= bool(seen.all())
-    del k, v, starts, inner, seg, seen
+    in_range = carries_keys(keys0, v, k, total)
+    ok &= in_range
+    if in_range:
+        seen = torch.zeros(total, dtype=torch.bool, device=dev)
+        seen[v] = True
+        ok &= bool(seen.all())
+        del seen
+    del k, v, starts, inner, seg
     log(f"bench: verified {ok}")
 
     times = timed(call, args.steps, args.warmup)
@@ -612,7 +624,7 @@ def bench_msd(args):
         ok = bool((k[1:] >= k[:-1]).all())
         eq = k[1:] == k[:-1]
         ok &= bool((v[1:][eq] > v[:-1][eq]).all())
-        ok &= bool(((keys0.to(torch.int64) & 0xFFFFFFFF)[v] == k).all())
+        ok &= carries_keys(keys0, v, k, n)
         del k, v, eq
         res[name] = {"ms_per_sort": float(np.mean(times)), "min_ms": float(np.min(times)),
                      "keys_per_s": n / (np.mean(times) / 1e3), "peak_extra_bytes": int(extra),

@@ -299,6 +299,7 @@ def test_structured_u64_2e30(dist):
     eq = keys[1:] == keys[:-1]
     assert bool((vals[1:][eq] > vals[:-1][eq]).all())
     del eq
+    assert bool(((vals >= 0) & (vals < n)).all())  # before indexing with them
     seen = torch.zeros(n, dtype=torch.bool, device=DEV)
     seen[vals.long()] = True
     assert bool(seen.all())
