@@ -179,6 +179,13 @@ E2E = [
     ("reverse", 1 << 20, 4, 4, 8, 1024),
     ("uniform", 2, 4, 4, 8, 1024),
     ("uniform", 65, 4, 4, 8, 64),
+    ("uniform", 0, 4, 4, 8, 1024),            # empty
+    ("uniform", 1, 8, 8, 8, 1024),
+    ("uniform", 1024, 4, 4, 8, 1024),         # exactly one block
+    ("uniform", 2 * 256 * 64, 4, 4, 8, 64),   # exactly the 2 sigma b of the head blocks
+    ("uniform", 2000, 8, 4, 1, 64),           # 1-bit digits: 64 rounds, the most there are
+    ("zipf", 30000, 4, 4, 2, 64),
+    ("few", 40000, 4, 4, 6, 256),
 ]
 
 
