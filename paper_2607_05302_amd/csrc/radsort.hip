@@ -1374,9 +1374,11 @@ int radsort_copy(void* dst, const void* src, uint64_t bytes, void* stream)
     int dev = 0, cus = 0;
     RS_HIP(hipGetDevice(&dev));
     RS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // 8 workgroups of 256 threads per CU, fewer when there is less to copy
+    // one workgroup of 256 threads per CU (fewer when there is less to copy): with
+    // 4 words in flight per thread this is the fastest of the shapes measured on
+    // MI355X (5.7 TB/s for 2 GiB; 8 workgroups per CU: 4.7 TB/s, 2: 5.5 TB/s)
     const uint64_t want = (words + 4 * 256 - 1) / (4 * 256);
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, 8ull * cus));
+    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)cus));
     hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, (hipStream_t)stream,
                        (u32x4*)dst, (const u32x4*)src, words,
                        (uint8_t*)dst + words * 16, (const uint8_t*)src + words * 16, tail);
