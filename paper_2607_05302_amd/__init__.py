@@ -171,8 +171,10 @@ def _validate(keys, payload):
     return _width(keys), (_width(payload) if payload is not None else 0)
 
 
-def workspace_bytes(n, key_bytes=4, payload_bytes=0, digit_bits=8, block_elems=1024) -> int:
-    o = _opts(block_elems)
+def workspace_bytes(n, key_bytes=4, payload_bytes=0, digit_bits=8, block_elems=1024,
+                    shared=False) -> int:
+    """radsort_workspace_bytes; shared: for calls made with shared=True."""
+    o = _opts(block_elems, None, F_SHARED if shared else 0)
     return int(load().radsort_workspace_bytes(n, key_bytes, payload_bytes, digit_bits,
                                               ctypes.byref(o)))
 

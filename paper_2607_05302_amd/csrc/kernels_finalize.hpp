@@ -67,13 +67,16 @@ inline uint32_t fin_job(uint32_t npi)
     return j;
 }
 
-inline uint64_t fin_scratch_bytes(uint32_t npi, uint64_t n, uint32_t b, uint32_t elem_bytes)
+// Finalize scratch; `temps`: with the two temporary blocks per job that only the
+// two-kernel form of F1 uses (shared GPU, or a state the cooperative form cannot cover)
+inline uint64_t fin_scratch_bytes(uint32_t npi, uint64_t n, uint32_t b, uint32_t elem_bytes,
+                                  bool temps)
 {
     const uint32_t job = fin_job(npi);
     uint64_t jobs = (npi + job - 1) / job;
     uint64_t sums = (npi + kScanTile - 1) / kScanTile + 1;
     return 6 * fin_align(4ull * npi) + fin_align(4 * sums) + fin_align(4 * fin_flag_words(npi, n)) +
-           fin_align(2 * jobs * (uint64_t)b * elem_bytes);
+           (temps ? fin_align(2 * jobs * (uint64_t)b * elem_bytes) : 0);
 }
 
 template <int KB, int VB>
@@ -548,6 +551,33 @@ constexpr uint32_t kFinLdsThreads = 512;
 constexpr uint32_t kFinLdsBytes = 128u << 10;  // dynamic LDS for saved heads
 constexpr uint32_t kFinLdsJobMax = 4096;       // nodes per job held in LDS
 
+// The cooperative form's shape for n_pi nodes on lds_grid workgroups (one per
+// compute unit): jpw jobs per workgroup, up to 8 as the LDS holds their heads
+// (2 jpw blocks of b records), fewer for small states so that their jobs of 16
+// nodes still spread over the workgroups; jobs of at most kFinLdsJobMax nodes.
+// covers: every node falls into one of the grid's jobs (else the two-kernel
+// form of F1 must run).
+struct FinCoop {
+    uint32_t jpw = 0, job = 0, grid = 0;
+    bool covers = false;
+};
+inline FinCoop fin_coop(uint32_t npi, uint32_t b, uint32_t elem_bytes, uint32_t lds_grid)
+{
+    FinCoop c;
+    if (!lds_grid) return c;
+    const uint64_t head_bytes = (uint64_t)b * elem_bytes;
+    const uint64_t jpw_fill = (npi + 16ull * lds_grid - 1) / (16ull * lds_grid);
+    c.jpw = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(8, kFinLdsBytes / (2 * head_bytes)),
+                                         std::max<uint64_t>(1, jpw_fill));
+    if (!c.jpw) return c;
+    uint64_t job = (npi + (uint64_t)lds_grid * c.jpw - 1) / ((uint64_t)lds_grid * c.jpw);
+    c.job = (uint32_t)std::max<uint64_t>(16, std::min<uint64_t>(job, kFinLdsJobMax));
+    c.grid = (uint32_t)std::min<uint64_t>(lds_grid, (npi + (uint64_t)c.job * c.jpw - 1) /
+                                                        ((uint64_t)c.job * c.jpw));
+    c.covers = (uint64_t)c.grid * c.jpw * c.job >= npi;
+    return c;
+}
+
 template <int KB, int VB, int VEC>
 __global__ __launch_bounds__(kFinLdsThreads) void k_fin_move_lds(
     FinArgs<KB, VB> a, FinArrays f, const uint32_t* rank, const uint32_t* clen,
@@ -847,10 +877,14 @@ template <int KB, int VB> constexpr int fin_chunk() { return (KB + VB >= 12) ? 4
 // compact_grid = 0 selects the dynamic compaction (one workgroup per chunk);
 // lds_grid = 0 the two-kernel F1 with heads saved in global memory, else the
 // cooperative F1 on lds_grid workgroups (one per compute unit)
+// temps: the scratch holds the two-kernel form's temporary blocks (fin_scratch_bytes);
+// without them a state the cooperative form cannot cover returns -2 before any launch
 template <int KB, int VB>
 int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_grid,
-                      hipStream_t s)
+                      bool temps, hipStream_t s)
 {
+    const FinCoop coop = fin_coop(a.npi, 1u << a.log2b, KB + VB, lds_grid);
+    if (!coop.covers && !temps) return -2;
     const uint32_t npi = a.npi, b = 1u << a.log2b;
     FinArrays f = fin_arrays(a.scratch, npi, a.n, a.spare_pi, a.spare_blen);
     const uint32_t grid = std::min<uint32_t>((npi + 255) / 256, 8192);
@@ -899,24 +933,10 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
     const bool wide = b >= 64 && (((uintptr_t)a.Ak | (uintptr_t)a.Av | (uintptr_t)a.Tk |
                                    (uintptr_t)a.Tv | (uintptr_t)f.temps) & 15) == 0;
     const uint64_t head_bytes = (uint64_t)b * (KB + VB);
-    // jobs per workgroup: up to 8 (as the LDS allows), fewer for small states so that
-    // their jobs of 16 nodes still spread over lds_grid workgroups
-    const uint64_t jpw_fill = lds_grid ? (npi + 16ull * lds_grid - 1) / (16ull * lds_grid) : 1;
-    const uint32_t jpw = (uint32_t)std::min<uint64_t>(
-        std::min<uint64_t>(8, kFinLdsBytes / (2 * head_bytes)), std::max<uint64_t>(1, jpw_fill));
-    // the cooperative form: jobs of at most kFinLdsJobMax nodes, jpw per workgroup;
-    // it must cover every node (at most n_pi of them), else the two-kernel form runs
-    uint32_t job = 0, cgrid = 0;
-    bool coop = false;
-    if (lds_grid && jpw > 0) {
-        job = (uint32_t)((npi + (uint64_t)lds_grid * jpw - 1) / ((uint64_t)lds_grid * jpw));
-        job = std::max<uint32_t>(16, std::min<uint32_t>(job, kFinLdsJobMax));
-        cgrid = (uint32_t)std::min<uint64_t>(lds_grid, (npi + (uint64_t)job * jpw - 1) /
-                                                           ((uint64_t)job * jpw));
-        coop = (uint64_t)cgrid * jpw * job >= npi;
-    }
-    if (coop) {
-        const uint32_t grid = cgrid;
+    // the cooperative form when it covers every node, else the two-kernel form
+    if (coop.covers) {
+        uint32_t job = coop.job, jpw = coop.jpw;
+        const uint32_t grid = coop.grid;
         const uint32_t lds = (uint32_t)(2 * jpw * head_bytes);
         void* args[] = {(void*)&a, (void*)&f, (void*)&rank, (void*)&clen, (void*)&M_ptr,
                         (void*)&job, (void*)&jpw};

@@ -100,6 +100,7 @@ struct Geo {
     uint32_t st_log2 = 0;                 // tiles per super-tile: 2^st_log2
     uint32_t supers = 0, oop_supers = 0;  // super-tiles of a Radsort / out-of-place round
     uint32_t oop_E = 0, oop_st_log2 = 0;  // tile and super-tile of the out-of-place round
+    bool fin_temps = false;  // finalize scratch holds the two-kernel F1's temporary blocks
 };
 
 // Workspace regions (byte offsets), each 256-byte aligned.
@@ -125,6 +126,19 @@ uint32_t tile_elems(uint32_t kb, uint32_t vb, uint32_t bits, bool oop)
 {
     if (bits > 8) return oop ? tile_elems_t<true, true>(kb, vb) : tile_elems_t<true, false>(kb, vb);
     return oop ? tile_elems_t<false, true>(kb, vb) : tile_elems_t<false, false>(kb, vb);
+}
+
+// Compute units of the current device; 256 (an MI355X) when no device answers.
+uint32_t device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    return (uint32_t)cus;
 }
 
 int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bits,
@@ -181,11 +195,19 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     g.oop_st_log2 = super_log2(g.oop_E);
     const uint64_t oop_tiles = (n + g.oop_E - 1) / g.oop_E;
     g.oop_supers = (uint32_t)((oop_tiles + (1u << g.oop_st_log2) - 1) >> g.oop_st_log2);
+    // F1 of finalize runs cooperatively on one workgroup per compute unit unless the
+    // GPU is shared or that grid cannot cover the state; only the other form needs
+    // temporary blocks in the workspace
+    const bool shared = opts && (opts->flags & RADSORT_F_SHARED);
+    g.fin_temps = shared || !fin_coop(g.npi, g.b, g.kb + g.vb, device_cus()).covers;
     return RADSORT_OK;
 }
 
 // Finalize scratch (parallel Alg. 7): see kernels_finalize.hpp.
-uint64_t finalize_bytes(const Geo& g) { return fin_scratch_bytes(g.npi, g.n, g.b, g.kb + g.vb); }
+uint64_t finalize_bytes(const Geo& g)
+{
+    return fin_scratch_bytes(g.npi, g.n, g.b, g.kb + g.vb, g.fin_temps);
+}
 
 Layout make_layout(const Geo& g, bool oop)
 {
@@ -669,8 +691,8 @@ template <int KB, int VB> struct Ops {
             RS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
             cus = (uint32_t)n_cu;
         }
-        int rc = finalize_parallel<KB, VB>(a, (uint32_t)cap, cus, s) ? RADSORT_E_DEVICE
-                                                                      : RADSORT_OK;
+        const int fr = finalize_parallel<KB, VB>(a, (uint32_t)cap, cus, g.fin_temps, s);
+        int rc = fr == -2 ? RADSORT_E_NOMEM : fr ? RADSORT_E_DEVICE : RADSORT_OK;
         g_timer.mark(kFinEnd, 0, s);
         return rc;
     }
@@ -914,6 +936,7 @@ int make_seg_plan(SegPlan& P, const uint64_t* off, uint32_t nseg, int kb, int vb
         SegChoice c = seg_choice(tuning, n);
         radsort_opts o = opts ? *opts : radsort_opts{};
         o.block_elems = c.b;
+        o.flags |= RADSORT_F_SHARED;  // the lanes run concurrently (run_one)
         Geo g;
         int rc = make_geo(g, n, kb, vb, (int)c.bits, &o);
         if (rc) return rc;
@@ -1010,6 +1033,7 @@ int run_one(void* keys, void* vals, uint64_t n, int kb, int vb, SegChoice c, uin
 {
     radsort_opts o{};
     o.block_elems = c.b;
+    o.flags = RADSORT_F_SHARED;  // sized as the plan sized it
     o.workspace = ws;
     o.workspace_bytes = ws_bytes;
     radsort_state* st = nullptr;
@@ -1612,7 +1636,7 @@ int radsort_sort_pairs_noalloc(void* keys, void* payload, uint64_t n, int key_by
     if (rc) return rc;
     radsort_opts o{};
     o.block_elems = block_elems;
-    o.flags = flags;
+    o.flags = flags | RADSORT_F_SHARED;  // the launch forms below
     Geo g;
     rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, &o);
     if (rc) return rc;

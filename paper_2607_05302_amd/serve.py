@@ -66,8 +66,10 @@ def region(req: Request, method: str, block: int = 1024):
     """Byte offsets of the keys, the payload and the workspace within a request's
     region, and the region's size."""
     import paper_2607_05302_amd as radsort
-    wsb = (radsort.workspace_bytes if method == "radsort" else radsort.oop_workspace_bytes)(
-        req.n, req.key_bytes, 4, 8, block)
+    if method == "radsort":  # its sorts run with shared=True
+        wsb = radsort.workspace_bytes(req.n, req.key_bytes, 4, 8, block, shared=True)
+    else:
+        wsb = radsort.oop_workspace_bytes(req.n, req.key_bytes, 4, 8, block)
     o_v = _align(req.n * req.key_bytes)
     o_w = o_v + _align(req.n * 4)
     return 0, o_v, o_w, o_w + _align(wsb)

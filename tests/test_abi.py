@@ -214,3 +214,25 @@ def test_copy_argument_errors():
     assert lib.radsort_copy(ctypes.c_void_p(0x1004), fake, 16, None) == radsort.E_INVALID
     assert lib.radsort_copy(fake, ctypes.c_void_p(0x1008), 16, None) == radsort.E_INVALID
     assert lib.radsort_copy(None, None, 0, None) == radsort.OK
+
+
+def test_shared_calls_need_their_own_workspace_size():
+    """With RADSORT_F_SHARED finalize's block permutation takes its two-kernel form,
+    whose temporary blocks the workspace must hold: the size for shared calls is at
+    least the other, and a workspace sized without the flag is refused by a shared
+    call before any launch."""
+    lib = radsort.load()
+    n = 1 << 28  # large enough that the temporaries outgrow the ring they share memory with
+    plain = radsort.workspace_bytes(n, 4, 4, 8, 1024)
+    shared = radsort.workspace_bytes(n, 4, 4, 8, 1024, shared=True)
+    assert shared > plain > 0
+    assert radsort.workspace_bytes(1 << 24, 4, 4, 8, 1024, shared=True) >= \
+        radsort.workspace_bytes(1 << 24, 4, 4, 8, 1024)
+    o = radsort.Opts()
+    o.block_elems = 1024
+    o.workspace = 0x1000  # never dereferenced: the size check comes first
+    o.workspace_bytes = plain
+    o.flags = radsort.F_SHARED
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.radsort_sort_pairs(fake, fake, n, 4, 4, 8, ctypes.byref(o), None) == \
+        radsort.E_NOMEM

@@ -65,8 +65,10 @@ def test_results_alone_and_in_the_mix(method):
 def test_workspace_error_reads_clear_after_shared_sorts(method, n, kb):
     req = serve.Request(0, 0.0, n, kb, 0x77 + n)
     keys, vals = drawn(req)
-    wsb = (radsort.workspace_bytes if method == "radsort" else radsort.oop_workspace_bytes)(
-        n, kb, 4, 8, 1024)
+    if method == "radsort":  # sized for a call with shared=True
+        wsb = radsort.workspace_bytes(n, kb, 4, 8, 1024, shared=True)
+    else:
+        wsb = radsort.oop_workspace_bytes(n, kb, 4, 8, 1024)
     ws = torch.full((wsb,), 0xFF, dtype=torch.uint8, device=DEV)
     sort = radsort.sort_ if method == "radsort" else radsort.oop_sort_
     sort(keys, vals, workspace=ws, shared=True)
