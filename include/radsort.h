@@ -175,11 +175,14 @@ int radsort_sort(void* keys, uint64_t n, int key_bytes, int digit_bits, void* st
  * blocks T (2 sigma b elements, Sec. 2.1), two n_pi-entry block permutations,
  * the per-round closed forms, the digit counts and look-back status ring and the
  * finalize scratch (which reuses the ring's memory).  The size depends on
- * opts->flags: with RADSORT_F_SHARED the finalize scratch also holds two blocks
- * per job of its block permutation (the form a shared GPU runs), which a call
- * with that flag needs; and on the current device's compute-unit count (256
- * assumed when no device answers), which decides whether the permutation's
- * cooperative form covers the state.  0 on invalid arguments. */
+ * opts->flags and on the current device's compute-unit count (256 assumed when no
+ * device answers), which decides whether the cooperative form of finalize's block
+ * permutation covers the state.  Without RADSORT_F_SHARED, when it does, the last
+ * round is packed: each bucket starts at the offset its final position has within
+ * a block, so that finalize only permutes blocks (no compaction), which takes
+ * sigma more blocks of b elements and n_pi + sigma entries per permutation.  With
+ * RADSORT_F_SHARED the finalize scratch instead holds two blocks per job of the
+ * permutation's two-kernel form.  0 on invalid arguments. */
 uint64_t radsort_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes,
                                  int digit_bits, const radsort_opts* opts);
 

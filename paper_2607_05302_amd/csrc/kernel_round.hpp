@@ -105,6 +105,15 @@ struct TileArgs {
     uint32_t* consumed;      // ordering-check builds only: per physical block, the tag of
     uint32_t tag;            // the round whose loads of it returned last; or null
     uint32_t tag_mark;       // the tag the marks carry (differs only to test the check)
+    // The packed round (the last before finalize; null / npi otherwise): bucket d
+    // starts at offset est[d] mod b of its head block (plan_round), and the pool of
+    // draws is sigma extra blocks X (physical npi .. npi + sigma - 1) followed by
+    // the input blocks in logical order, which keeps every draw behind the blocks
+    // already read although the offsets make buckets draw up to sigma blocks early.
+    const uint32_t* pack_est;
+    K* Xk;
+    V* Xv;
+    uint32_t npi_x;          // physical blocks a draw can name: npi, + sigma when packed
 };
 
 // Timeline builds (RS_TIMELINE defined): thread 0 of each workgroup records the
@@ -570,6 +579,8 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
             }
         }
         base[d] = sbase + acc;
+        if constexpr (!OOP)
+            if (a.pack_est) base[d] += a.pack_est[d] & (b - 1);  // the packed round's offset
     }
     __syncthreads();
     RS_STAMP(4);
@@ -623,6 +634,11 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
         }
     } else {
         // ---- block draws ----------------------------------------------------------------
+        // the block a draw names: Eq. 1, or one of the packed round's extra blocks
+        auto out_block = [&](auto* A, auto* T, auto* X, uint32_t j) {
+            return j < a.npi ? blockat(A, T, j, two_sigma, log2b)
+                             : X + ((uint64_t)(j - a.npi) << log2b);
+        };
         // Request the block that takes each digit's first elements (drawn by an
         // earlier tile) now; it is used after this tile's own draws are out.
         uint32_t first = kEmpty;  // pi_new entry of that block, for digit tid
@@ -632,7 +648,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
             const uint32_t nfill = ((bs + c) >> log2b) - q0;
             const uint32_t nwrite = c ? ((bs + c - 1) >> log2b) - q0 + 1 : 0u;
             const uint32_t L = a.S[d] + q0;
-            if (d == tid && c && q0 > 0 && L < a.npi) first = ld_agent(a.pi_new + L);
+            if (d == tid && c && q0 > 0 && L < a.npi_x) first = ld_agent(a.pi_new + L);
             nfw[d] = (nfill << 16) | nwrite;
             tbo[d] = nwrite;
             if constexpr (!SEQ) fbo[d] = nfill;
@@ -677,16 +693,24 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
             }
         }
         // request the pool entries of the draws, and the done words of the
-        // earlier tiles whose input blocks they are
+        // earlier tiles whose input blocks they are.  Draw k of the round takes pool
+        // entry k: the input block sigma + k (logical), or in the packed round the
+        // extra block npi + k for k < sigma and then the input block k.
+        const bool packed = a.pack_est != nullptr;
+        auto pool_entry = [&](uint32_t k) -> uint32_t {
+            if (packed) return k < sigma ? a.npi + k : (k < a.npi ? a.pi_old[k] : a.npi_x);
+            const uint32_t h = sigma + k;
+            return h < a.npi ? a.pi_old[h] : a.npi_x;
+        };
         uint32_t pv = 0;
-        if (tid < nfills) {
-            const uint32_t h = sigma + F + tid;
-            pv = h < a.npi ? a.pi_old[h] : a.npi;
-        }
+        if (tid < nfills) pv = pool_entry(F + tid);
+        // input blocks (counted from the round's first) among the drawn entries
+        const uint32_t in_lo = packed ? (F > sigma ? F - sigma : 0u) : F;
+        const uint32_t in_hi = packed ? (F + nfills > sigma ? F + nfills - sigma : 0u) : F + nfills;
         uint32_t olo = 0, ohi = 0, dv = ~0u;
-        if (nfills) {
-            olo = (uint32_t)(((uint64_t)F << log2b) / E);
-            ohi = min<uint32_t>((uint32_t)((((uint64_t)(F + nfills) << log2b) - 1) / E) + 1, st0);
+        if (in_hi > in_lo) {
+            olo = (uint32_t)(((uint64_t)in_lo << log2b) / E);
+            ohi = min<uint32_t>((uint32_t)((((uint64_t)in_hi << log2b) - 1) / E) + 1, st0);
             if (olo + tid < ohi) dv = ld_agent(a.done + ((olo + tid) & wmask));
         }
         if constexpr (SMAX > NT) {
@@ -725,10 +749,8 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
             for (uint32_t i = tid; i < E / 32; i += NT) fpref[i] = __popc(fmask[i]);
         }
         if (tid < nfills) pool[tid] = pv;
-        for (uint32_t i = tid + NT; i < nfills; i += NT) {  // more draws than threads: rare
-            const uint32_t h = sigma + F + i;
-            pool[i] = h < a.npi ? a.pi_old[h] : a.npi;
-        }
+        for (uint32_t i = tid + NT; i < nfills; i += NT)  // more draws than threads: rare
+            pool[i] = pool_entry(F + i);
         __syncthreads();
         RS_STAMP(11);
 #ifdef RS_DEBUG_ORDER
@@ -760,8 +782,8 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                     r = fbo[d] + i - 1;
                 }
                 const uint32_t L = Sd + q0 + i;
-                uint32_t phys = r < nfills ? pool[r] : a.npi;
-                if (phys < a.npi && L < a.npi) {
+                uint32_t phys = r < nfills ? pool[r] : a.npi_x;
+                if (phys < a.npi_x && L < a.npi_x) {
                     st_agent(a.pi_new + L, phys);
                 } else {
                     raise_error(a.err, kErrBounds);
@@ -779,7 +801,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                 uint32_t phys = d == tid ? first : kEmpty;
                 if (q0 == 0) {
                     phys = a.pi_old[d];
-                } else if (a.S[d] + q0 >= a.npi) {
+                } else if (a.S[d] + q0 >= a.npi_x) {
                     raise_error(a.err, kErrBounds);
                     phys = 0;
                 } else {
@@ -797,7 +819,7 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
         __syncthreads();
         RS_STAMP(5);
         for (uint32_t e = tid; e < nent; e += NT) {
-            if (tphys[e] >= a.npi) {  // never for a consistent state: send the writes to T
+            if (tphys[e] >= a.npi_x) {  // never for a consistent state: send the writes to T
                 raise_error(a.err, kErrBounds);
                 tphys[e] = 0;
             }
@@ -808,9 +830,9 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
             uint64_t* ptab = (uint64_t*)uni;
             for (uint32_t e = tid; e < nent; e += NT) {
                 const uint32_t j = tphys[e];
-                ptab[2 * e] = (uint64_t)(uintptr_t)blockat(a.Ak, a.Tk, j, two_sigma, log2b);
+                ptab[2 * e] = (uint64_t)(uintptr_t)out_block(a.Ak, a.Tk, a.Xk, j);
                 if constexpr (VB != 0)
-                    ptab[2 * e + 1] = (uint64_t)(uintptr_t)blockat(a.Av, a.Tv, j, two_sigma, log2b);
+                    ptab[2 * e + 1] = (uint64_t)(uintptr_t)out_block(a.Av, a.Tv, a.Xv, j);
             }
             __syncthreads();
             RS_STAMP(6);
@@ -887,8 +909,8 @@ __attribute__((amdgpu_waves_per_eu(SH::OCC))) void k_round(TileArgs<KB, VB> a)
                 const uint32_t r = p + x.x;
                 const uint32_t j = tphys[x.y + (r >> log2b)];
                 const uint32_t off = r & (b - 1);
-                blockat(a.Ak, a.Tk, j, two_sigma, log2b)[off] = k;
-                if constexpr (VB != 0) blockat(a.Av, a.Tv, j, two_sigma, log2b)[off] = lv[p];
+                out_block(a.Ak, a.Tk, a.Xk, j)[off] = k;
+                if constexpr (VB != 0) out_block(a.Av, a.Tv, a.Xv, j)[off] = lv[p];
             }
         }
     }

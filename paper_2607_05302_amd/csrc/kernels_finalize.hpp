@@ -27,6 +27,11 @@
 // After truncate (Alg. 8) the same steps apply with n_pi and the A blocks of the
 // original array: the allocated blocks sigma .. f-1 are fewer, F1 leaves the
 // blocks past f alone as unallocated, and F2 reads nothing from them.
+//
+// A packed state (its last round packed: every element already sits at the slot
+// of its final position) needs no F2 and no F3: F1 moves each block to the home
+// k_pack_homes gives it, over n_pi + sigma blocks, and k_pack_merge copies the
+// slots of the at most 2 sigma blocks that do not fill a block of A into place.
 #pragma once
 
 #include <hip/hip_cooperative_groups.h>
@@ -98,6 +103,24 @@ struct FinArgs {
     uint8_t* scratch;
     uint32_t* spare_pi;  // the other pi buffer (n_pi words), free during finalize
     uint32_t* spare_blen;  // the block-length array (n_pi words), free during finalize
+    // A packed state (its last round packed, plan_round): npi counts the sigma extra
+    // blocks X too (physical npi_eq .. npi - 1), and F1 moves every logical block to
+    // the home k_pack_homes gives it.  Otherwise pack is null and npi_eq = npi.
+    K* Xk;
+    V* Xv;
+    uint32_t npi_eq;
+    const uint32_t* est;   // packed: element start of each bucket
+    const uint32_t* S;     // packed: first logical block of each bucket
+    uint32_t* pack;        // packed: 2 sigma + 2 words (k_pack_table), else null
+    // the block of physical index j: Eq. 1, or an extra block of a packed state
+    __device__ K* kblock(uint32_t j) const
+    {
+        return j < npi_eq ? blockat(Ak, Tk, j, 2 * sigma, log2b) : Xk + ((uint64_t)(j - npi_eq) << log2b);
+    }
+    __device__ V* vblock(uint32_t j) const
+    {
+        return j < npi_eq ? blockat(Av, Tv, j, 2 * sigma, log2b) : Xv + ((uint64_t)(j - npi_eq) << log2b);
+    }
 };
 
 struct FinArrays {
@@ -131,18 +154,24 @@ inline FinArrays fin_arrays(uint8_t* s, uint32_t npi, uint64_t n, uint32_t* spar
 
 // next(pi[L]) = rot(L); the top bit marks a node whose content is unallocated.
 // Doubling state: J = next, (V, O) = (p, 0).
+// homes (packed states): next(pi[L]) = homes[L] and its top bit marks no data.
 __global__ void k_fin_init(const uint32_t* __restrict__ pi, const uint32_t* __restrict__ f_ptr,
                            uint32_t sigma, uint32_t npi, uint32_t* __restrict__ nxt,
                            uint32_t* __restrict__ J, uint32_t* __restrict__ V,
-                           uint32_t* __restrict__ O)
+                           uint32_t* __restrict__ O, const uint32_t* __restrict__ homes)
 {
     const uint32_t f = *f_ptr;
     for (uint32_t L = blockIdx.x * blockDim.x + threadIdx.x; L < npi;
          L += gridDim.x * blockDim.x) {
         const uint32_t p = pi[L];
         if (p >= npi) continue;  // never for a permutation
-        const uint32_t to = L + sigma < npi ? L + sigma : L + sigma - npi;
-        const bool garbage = L < sigma || L >= f;
+        uint32_t to = L + sigma < npi ? L + sigma : L + sigma - npi;
+        bool garbage = L < sigma || L >= f;
+        if (homes) {
+            to = homes[L] & ~kGarbage;
+            garbage = homes[L] & kGarbage;
+            if (to >= npi) to = p;  // never for a consistent table
+        }
         nxt[p] = to | (garbage ? kGarbage : 0u);
         J[p] = to;
         V[p] = p;
@@ -220,7 +249,8 @@ __global__ __launch_bounds__(NT) void k_fin_prep_small(
     const uint32_t* __restrict__ Pidx, const uint32_t* __restrict__ Plen, uint32_t sigma,
     uint32_t log2b, uint32_t npi, uint32_t* __restrict__ rank, uint32_t* __restrict__ clen,
     uint32_t* __restrict__ ord, uint32_t* __restrict__ M_out, uint32_t* __restrict__ gap,
-    uint32_t* __restrict__ flags, uint64_t nflags, uint32_t* __restrict__ err)
+    uint32_t* __restrict__ flags, uint64_t nflags, uint32_t* __restrict__ err,
+    const uint32_t* __restrict__ homes)
 {
     constexpr uint32_t PER = kFinSmallNodes / NT;  // nodes per thread
     __shared__ uint32_t nx[kFinSmallNodes], J[kFinSmallNodes], Vs[kFinSmallNodes],
@@ -239,8 +269,14 @@ __global__ __launch_bounds__(NT) void k_fin_prep_small(
             raise_error(err, kErrBounds);
             p = L;
         }
-        const uint32_t to = L + sigma < npi ? L + sigma : L + sigma - npi;
-        nx[p] = to | ((L < sigma || L >= f) ? kGarbage : 0u);
+        uint32_t to = L + sigma < npi ? L + sigma : L + sigma - npi;
+        uint32_t gb = (L < sigma || L >= f) ? kGarbage : 0u;
+        if (homes) {  // packed state
+            to = homes[L] & ~kGarbage;
+            gb = homes[L] & kGarbage;
+            if (to >= npi) to = p;  // never for a consistent table
+        }
+        nx[p] = to | gb;
         J[p] = to;
         Vs[p] = p;
         Os[p] = 0;
@@ -397,7 +433,6 @@ __global__ __launch_bounds__(256) void k_fin_save(FinArgs<KB, VB> a, FinArrays f
     using K = typename UInt<KB>::T;
     using V = typename Payload<VB>::T;
     const uint32_t M = min(*M_ptr, a.npi), j = blockIdx.x, b = 1u << a.log2b;
-    const uint32_t two_sigma = 2 * a.sigma;
     if (j * a.job >= M) return;
     uint32_t h[2];
     job_heads(f.ord, rank, clen, j, a.job, M, a.npi, h[0], h[1]);
@@ -410,9 +445,9 @@ __global__ __launch_bounds__(256) void k_fin_save(FinArgs<KB, VB> a, FinArrays f
             continue;
         }
         const uint64_t slot = 2ull * j + s;
-        copy_block_cols(tk + (slot << a.log2b), blockat(a.Ak, a.Tk, h[s], two_sigma, a.log2b), b);
+        copy_block_cols(tk + (slot << a.log2b), a.kblock(h[s]), b);
         if constexpr (VB != 0)
-            copy_block_cols(tv + (slot << a.log2b), blockat(a.Av, a.Tv, h[s], two_sigma, a.log2b), b);
+            copy_block_cols(tv + (slot << a.log2b), a.vblock(h[s]), b);
     }
 }
 
@@ -439,7 +474,6 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
     using KE = typename UInt<KB>::T;
     using VE = typename Payload<VB>::T;
     const uint32_t M = min(*M_ptr, a.npi), j = blockIdx.x, b = 1u << a.log2b;
-    const uint32_t two_sigma = 2 * a.sigma;
     const uint32_t i0 = j * a.job;
     if (i0 >= M) return;
     const uint32_t i1 = min(M, i0 + a.job);
@@ -461,10 +495,10 @@ __global__ __launch_bounds__(kFinCols) void k_fin_move(FinArgs<KB, VB> a, FinArr
     // T block (only possible for a corrupt state, which also raises an error)
     auto safe = [&](uint32_t node) { return node < a.npi ? node : 0u; };
     auto addr_k = [&](uint32_t node) {
-        return (K*)(blockat(a.Ak, a.Tk, safe(node), two_sigma, log2b) + col);
+        return (K*)(a.kblock(safe(node)) + col);
     };
     auto addr_v = [&](uint32_t node) {
-        return (V*)(blockat(a.Av, a.Tv, safe(node), two_sigma, log2b) + col);
+        return (V*)(a.vblock(safe(node)) + col);
     };
 
     uint32_t i = i0;
@@ -592,7 +626,7 @@ __global__ __launch_bounds__(kFinLdsThreads) void k_fin_move_lds(
     // loads in flight per thread (twice the threads of k_fin_move, half the depth)
     constexpr uint32_t DEPTH = VEC == 1 ? kFinDepth : (KB + VB <= 8 ? 8u : 4u);
     const uint32_t M = min(*M_ptr, a.npi), b = 1u << a.log2b, log2b = a.log2b;
-    const uint32_t two_sigma = 2 * a.sigma, tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     KE* const hk_base = (KE*)saved;                                   // 2 jpw key blocks
     VE* const hv_base = (VE*)(saved + 2ull * jpw * ((uint64_t)b * KB)); // then payload
     auto safe = [&](uint32_t node) { return node < a.npi ? node : 0u; };
@@ -610,10 +644,10 @@ __global__ __launch_bounds__(kFinLdsThreads) void k_fin_move_lds(
                 continue;
             }
             const uint64_t slot = 2ull * k + q;
-            const KE* src = blockat(a.Ak, a.Tk, h[q], two_sigma, log2b);
+            const KE* src = a.kblock(h[q]);
             for (uint32_t c = tid; c < b; c += kFinLdsThreads) hk_base[(slot << log2b) + c] = src[c];
             if constexpr (VB != 0) {
-                const VE* sv = blockat(a.Av, a.Tv, h[q], two_sigma, log2b);
+                const VE* sv = a.vblock(h[q]);
                 for (uint32_t c = tid; c < b; c += kFinLdsThreads)
                     hv_base[(slot << log2b) + c] = sv[c];
             }
@@ -637,10 +671,10 @@ __global__ __launch_bounds__(kFinLdsThreads) void k_fin_move_lds(
             const uint32_t col = col0 + tid * VEC;
             const bool active = col < b;  // b is a multiple of VEC
             auto addr_k = [&](uint32_t node) {
-                return (K*)(blockat(a.Ak, a.Tk, safe(node), two_sigma, log2b) + col);
+                return (K*)(a.kblock(safe(node)) + col);
             };
             auto addr_v = [&](uint32_t node) {
-                return (V*)(blockat(a.Av, a.Tv, safe(node), two_sigma, log2b) + col);
+                return (V*)(a.vblock(safe(node)) + col);
             };
             uint32_t i = i0;
             while (i < i1) {
@@ -713,6 +747,146 @@ __global__ __launch_bounds__(kFinLdsThreads) void k_fin_move_lds(
                 i = e;
             }
         }
+    }
+}
+
+// ---- finalize of a packed state ------------------------------------------------------
+//
+// After the packed round, block q of bucket d holds the ranks whose final positions
+// lie in block g = floor(est[d] / b) + q of A, each at the slot it has there: slots
+// lo .. hi - 1 with lo = est[d] mod b for q = 0, else 0.  So the data needs no gap
+// closed, only blocks moved: every block g < floor(n/b) of A is the home of its
+// "primary", the block whose slots reach the end of g (exactly one per g).  Each
+// other block with data is the last block of its bucket, ending inside a block of
+// A or lying in the partial tail [floor(n/b) b, n); it moves to a spare block (of
+// T or X) and is copied into place afterwards (k_pack_merge), its slots only, over
+// the garbage the primary brought into those slots.  Blocks without data (the
+// head start, the unallocated ones, a bucket's empty head or empty last block)
+// take the spare blocks left.  Spare k is physical k for k < 2 sigma, else
+// npi_eq + k - 2 sigma.
+
+__device__ __forceinline__ uint32_t pack_spare(uint32_t k, uint32_t sigma, uint32_t npi_eq)
+{
+    return k < 2 * sigma ? k : npi_eq + (k - 2 * sigma);
+}
+
+// The bucket table (one workgroup): tab[d] = rank of bucket d's spare block among
+// those of buckets before it (~0: none), tab[sigma + d] = rank of its empty block
+// (~0: none), tab[2 sigma] and tab[2 sigma + 1] the totals.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_pack_table(const uint32_t* __restrict__ est, uint64_t n,
+                                                   uint32_t sigma, uint32_t log2b,
+                                                   uint32_t* __restrict__ tab)
+{
+    extern __shared__ uint32_t sh[];  // 2 sigma words
+    __shared__ uint32_t tmp[NT / 64 + 1];
+    const uint32_t b = 1u << log2b;
+    const uint64_t nA = n >> log2b;
+    for (uint32_t d = threadIdx.x; d < sigma; d += NT) {
+        const uint64_t e0 = est[d], e1 = d + 1 < sigma ? est[d + 1] : n;
+        const uint64_t c = e1 > e0 ? e1 - e0 : 0, o = e0 & (b - 1);
+        bool spare = false;
+        if (c) {
+            const uint64_t ql = (o + c - 1) >> log2b, gl = (e0 >> log2b) + ql;
+            const uint64_t hl = o + c - (ql << log2b);
+            spare = gl >= nA || hl < b;
+        }
+        sh[d] = spare;
+        sh[sigma + d] = c == 0 || ((o + c) & (b - 1)) == 0;
+    }
+    __syncthreads();
+    const uint32_t ns = block_excl_scan<NT>(sh, sigma, tmp);
+    const uint32_t ne = block_excl_scan<NT>(sh + sigma, sigma, tmp);
+    for (uint32_t d = threadIdx.x; d < sigma; d += NT) {
+        const uint64_t e0 = est[d], e1 = d + 1 < sigma ? est[d + 1] : n;
+        const uint64_t c = e1 > e0 ? e1 - e0 : 0, o = e0 & (b - 1);
+        bool spare = false;
+        if (c) {
+            const uint64_t ql = (o + c - 1) >> log2b, gl = (e0 >> log2b) + ql;
+            const uint64_t hl = o + c - (ql << log2b);
+            spare = gl >= nA || hl < b;
+        }
+        const bool empty = c == 0 || ((o + c) & (b - 1)) == 0;
+        tab[d] = spare ? sh[d] : ~0u;
+        tab[sigma + d] = empty ? sh[sigma + d] : ~0u;
+    }
+    if (threadIdx.x == 0) {
+        tab[2 * sigma] = ns;
+        tab[2 * sigma + 1] = ne;
+    }
+}
+
+// homes[L] for every logical block L < npi (npi = npi_eq + sigma): its primary's A
+// block, a spare block, or (top bit set) a spare block for a block without data.
+__global__ void k_pack_homes(const uint32_t* __restrict__ S, const uint32_t* __restrict__ est,
+                             const uint32_t* __restrict__ f_ptr, const uint32_t* __restrict__ tab,
+                             uint64_t n, uint32_t sigma, uint32_t log2b, uint32_t npi_eq,
+                             uint32_t npi, uint32_t* __restrict__ homes,
+                             uint32_t* __restrict__ err)
+{
+    const uint32_t b = 1u << log2b, f = min(*f_ptr, npi);
+    const uint64_t nA = n >> log2b;
+    const uint32_t ns = tab[2 * sigma], ne = tab[2 * sigma + 1];
+    for (uint32_t L = blockIdx.x * blockDim.x + threadIdx.x; L < npi;
+         L += gridDim.x * blockDim.x) {
+        uint32_t h;
+        if (L < sigma) {
+            h = pack_spare(ns + L, sigma, npi_eq) | kGarbage;
+        } else if (L >= f) {
+            h = pack_spare(ns + sigma + ne + (L - f), sigma, npi_eq) | kGarbage;
+        } else {
+            uint32_t lo_d = 0, hi_d = sigma;  // the last bucket d with S[d] <= L
+            while (hi_d - lo_d > 1) {
+                const uint32_t mid = (lo_d + hi_d) >> 1;
+                if (S[mid] <= L) lo_d = mid;
+                else hi_d = mid;
+            }
+            const uint32_t d = lo_d, q = L - S[d];
+            const uint64_t e0 = est[d], e1 = d + 1 < sigma ? est[d + 1] : n;
+            const uint64_t c = e1 > e0 ? e1 - e0 : 0, o = e0 & (b - 1);
+            const uint64_t start = (uint64_t)q << log2b, g = (e0 >> log2b) + q;
+            const uint64_t lo = q == 0 ? o : 0;
+            const uint64_t hi = o + c > start ? min<uint64_t>(b, o + c - start) : 0;
+            if (hi <= lo) {
+                const uint32_t r = tab[sigma + d];
+                h = pack_spare(ns + sigma + (r == ~0u ? 0 : r), sigma, npi_eq) | kGarbage;
+                if (r == ~0u) raise_error(err, kErrBounds);  // never for a consistent plan
+            } else if (g < nA && hi == b) {
+                h = 2 * sigma + (uint32_t)g;
+            } else {
+                const uint32_t r = tab[d];
+                h = pack_spare(r == ~0u ? 0 : r, sigma, npi_eq);
+                if (r == ~0u) raise_error(err, kErrBounds);  // never for a consistent plan
+            }
+        }
+        homes[L] = h;
+    }
+}
+
+// After F1: workgroup d copies the slots of bucket d's spare block (if it has one)
+// from that block into A.
+template <int KB, int VB>
+__global__ __launch_bounds__(256) void k_pack_merge(FinArgs<KB, VB> a)
+{
+    const uint32_t d = blockIdx.x, sigma = a.sigma, log2b = a.log2b, b = 1u << log2b;
+    const uint32_t r = a.pack[d];
+    if (r == ~0u) return;
+    const uint64_t e0 = a.est[d], e1 = d + 1 < sigma ? a.est[d + 1] : a.n;
+    const uint64_t c = e1 > e0 ? e1 - e0 : 0, o = e0 & (b - 1);
+    if (!c) return;
+    const uint64_t ql = (o + c - 1) >> log2b, g = (e0 >> log2b) + ql;
+    const uint64_t lo = ql == 0 ? o : 0, hi = o + c - (ql << log2b);
+    const uint64_t base = g << log2b;
+    if (base + hi > a.n || hi > b) {  // never for a consistent plan
+        if (threadIdx.x == 0) raise_error(a.err, kErrBounds);
+        return;
+    }
+    const uint32_t from = pack_spare(r, sigma, a.npi_eq);
+    const auto* sk = a.kblock(from);
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) a.Ak[base + i] = sk[i];
+    if constexpr (VB != 0) {
+        const auto* sv = a.vblock(from);
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += 256) a.Av[base + i] = sv[i];
     }
 }
 
@@ -884,7 +1058,7 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
                       bool temps, hipStream_t s)
 {
     const FinCoop coop = fin_coop(a.npi, 1u << a.log2b, KB + VB, lds_grid);
-    if (!coop.covers && !temps) return -2;
+    if (!coop.covers && (!temps || a.pack)) return -2;
     const uint32_t npi = a.npi, b = 1u << a.log2b;
     FinArrays f = fin_arrays(a.scratch, npi, a.n, a.spare_pi, a.spare_blen);
     const uint32_t grid = std::min<uint32_t>((npi + 255) / 256, 8192);
@@ -892,19 +1066,29 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
     uint32_t* clen = f.j1;
     const uint32_t* M_ptr;  // total number of nodes to move
     uint32_t* gap;          // F2's gap prefix
+    // a packed state: its bucket table, then every logical block's home (in o1,
+    // which the preparation below reads before it writes o1)
+    const uint32_t* homes = nullptr;
+    if (a.pack) {
+        hipLaunchKernelGGL(k_pack_table<256>, dim3(1), dim3(256), 8 * a.sigma, s, a.est, a.n,
+                           a.sigma, a.log2b, a.pack);
+        hipLaunchKernelGGL(k_pack_homes, dim3(grid), dim3(256), 0, s, a.S, a.est, a.f, a.pack,
+                           a.n, a.sigma, a.log2b, a.npi_eq, npi, f.o1, a.err);
+        homes = f.o1;
+    }
     const bool small = npi <= kFinSmallNodes;
     if (small) {
         // F1's preparation, F2's gaps and flags in one workgroup
         hipLaunchKernelGGL(k_fin_prep_small<1024>, dim3(1), dim3(1024), 0, s, a.pi, a.f, a.Pidx,
                            a.Plen, a.sigma, a.log2b, npi, rank, clen, f.ord, f.sums, f.o0,
-                           f.flags, f.nflags, a.err);
+                           f.flags, f.nflags, a.err, homes);
         M_ptr = f.sums;
         gap = f.o0;
     } else {
         // F1: cycles
         uint32_t *J[2] = {f.j0, f.j1}, *Vv[2] = {f.v0, f.v1}, *O[2] = {f.o0, f.o1};
         hipLaunchKernelGGL(k_fin_init, dim3(grid), dim3(256), 0, s, a.pi, a.f, a.sigma, npi,
-                           f.nxt, J[0], Vv[0], O[0]);
+                           f.nxt, J[0], Vv[0], O[0], homes);
         int cur = 0;
         for (uint64_t w = 1; w < npi; w <<= 1) {
             hipLaunchKernelGGL(k_fin_jump, dim3(grid), dim3(256), 0, s, J[cur], Vv[cur], O[cur],
@@ -921,13 +1105,16 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
         M_ptr = f.sums + tiles;
         hipLaunchKernelGGL(k_fin_order, dim3(grid), dim3(256), 0, s, f.nxt, V, rank, clen, scan,
                            f.ord, npi);
-        // F2's gap prefix goes where the doubling state was (free after k_fin_order)
+        // F2's gap prefix goes where the doubling state was (free after k_fin_order);
+        // a packed state has no F2
         gap = Ofin;
-        hipLaunchKernelGGL(k_fin_gaps, dim3(1), dim3(256), 4 * a.sigma, s, a.Pidx, a.Plen,
-                           a.sigma, a.log2b, npi, gap);
-        hipLaunchKernelGGL(k_fill_u32,
-                           dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
-                           dim3(256), 0, s, f.flags, f.nflags, 0u);
+        if (!a.pack) {
+            hipLaunchKernelGGL(k_fin_gaps, dim3(1), dim3(256), 4 * a.sigma, s, a.Pidx, a.Plen,
+                               a.sigma, a.log2b, npi, gap);
+            hipLaunchKernelGGL(k_fill_u32,
+                               dim3((uint32_t)std::min<uint64_t>((f.nflags + 255) / 256, 4096)),
+                               dim3(256), 0, s, f.flags, f.nflags, 0u);
+        }
     }
     // four columns per thread when every block start is 16-byte aligned
     const bool wide = b >= 64 && (((uintptr_t)a.Ak | (uintptr_t)a.Av | (uintptr_t)a.Tk |
@@ -960,6 +1147,11 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
         hipLaunchKernelGGL((k_fin_move<KB, VB, 1>), dim3(jobs, slices), dim3(kFinCols), 0, s, a, f,
                            rank, clen, M_ptr);
     }
+    }
+    // a packed state has no gaps to close: its blocks that do not end in A go in now
+    if (a.pack) {
+        hipLaunchKernelGGL((k_pack_merge<KB, VB>), dim3(a.sigma), dim3(256), 0, s, a);
+        return 0;
     }
     // F2: compaction
     const uint64_t positions = (a.n >> a.log2b) << a.log2b;

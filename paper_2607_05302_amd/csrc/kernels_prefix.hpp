@@ -26,7 +26,8 @@ constexpr int kMaxSuperBlocks = 2048;  // blocks of one super-tile held in LDS
 // With plan != 0 (a grid of at most kScanRows workgroups: one chunk) no csum is
 // kept: the last workgroup to finish, found by the counter *done (zero on
 // entry), runs the column scan of k_column_scan itself and then the round's
-// plan (plan == 2: with element starts), so that no scan kernel is needed.
+// plan (plan == 2: with element starts; 3: packed, see plan_round), so that no
+// scan kernel is needed.
 template <int KB, bool OOP, int NT>
 __global__ __launch_bounds__(NT) void k_supertile_counts(
     const typename UInt<KB>::T* __restrict__ Ak, const typename UInt<KB>::T* __restrict__ Tk,
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_supertile_counts(
     }
     __syncthreads();  // the totals row is written by this workgroup; h is free
     plan_round<NT>(cnt + (uint64_t)(rows - 1) * sigma, sigma, log2b, h, h + sigma, h + 2 * sigma,
-                   pp.S, pp.Pidx, pp.Plen, pp.f, plan == 2 ? pp.est : nullptr);
+                   pp.S, pp.Pidx, pp.Plen, pp.f, plan >= 2 ? pp.est : nullptr, plan == 3);
 }
 
 // In place, for every digit d: cnt[u * sigma + d] becomes sum_{u' < u} cnt[u' * sigma + d].
@@ -170,7 +171,8 @@ __global__ __launch_bounds__(NT) void k_column_scan(uint32_t* cnt, const uint32_
         extern __shared__ uint32_t sm[];
         __syncthreads();  // the totals row was written by this workgroup
         plan_round<NT>(cnt + (uint64_t)(rows - 1) * sigma, sigma, log2b, sm, sm + sigma,
-                       sm + 2 * sigma, p.S, p.Pidx, p.Plen, p.f, plan == 2 ? p.est : nullptr);
+                       sm + 2 * sigma, p.S, p.Pidx, p.Plen, p.f, plan >= 2 ? p.est : nullptr,
+                       plan == 3);
     }
 }
 

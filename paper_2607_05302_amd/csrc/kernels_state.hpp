@@ -103,26 +103,35 @@ struct PlanPtrs {
 // One round of the plan from the digit counts cnt[0..sigma) of its input.  C and
 // E are sigma words of LDS each, tmp NT/64 + 1; est may be null (Radsort itself
 // needs no element starts).  Contains barriers: every thread must call it.
+//
+// packed (a Radsort round that is the last before finalize; est given): bucket d
+// starts at offset o_d = est[d] mod b of its head block, so that its ranks sit at
+// the slots their final positions est[d] + rank have within blocks of A.  Its
+// blocks are those of o_d + c_d ranks: C[d] = 1 + floor((o_d + c_d) / b), the last
+// one partial with (o_d + c_d) mod b slots up to its end; the first one holds
+// slots o_d .. b - 1 only.
 template <int NT>
 __device__ void plan_round(const uint32_t* __restrict__ cnt, uint32_t sigma, uint32_t log2b,
                            uint32_t* C, uint32_t* E, uint32_t* tmp, uint32_t* __restrict__ S,
                            uint32_t* __restrict__ Pidx, uint32_t* __restrict__ Plen,
-                           uint32_t* __restrict__ f, uint32_t* __restrict__ est)
+                           uint32_t* __restrict__ f, uint32_t* __restrict__ est,
+                           bool packed = false)
 {
     const uint32_t b = 1u << log2b, tid = threadIdx.x;
-    for (uint32_t d = tid; d < sigma; d += NT) {
-        C[d] = 1 + (cnt[d] >> log2b);
-        E[d] = cnt[d];
-    }
+    for (uint32_t d = tid; d < sigma; d += NT) E[d] = cnt[d];
+    __syncthreads();
+    if (est) block_excl_scan<NT>(E, sigma, tmp);
+    // ranks of bucket d as the blocks see them: its count, plus o_d when packed
+    auto span = [&](uint32_t d) { return cnt[d] + (packed ? (E[d] & (b - 1)) : 0u); };
+    for (uint32_t d = tid; d < sigma; d += NT) C[d] = 1 + (span(d) >> log2b);
     __syncthreads();
     const uint32_t total = block_excl_scan<NT>(C, sigma, tmp);
-    if (est) block_excl_scan<NT>(E, sigma, tmp);
     for (uint32_t d = tid; d < sigma; d += NT) {
-        const uint32_t c = 1 + (cnt[d] >> log2b);
+        const uint32_t c = 1 + (span(d) >> log2b);
         const uint32_t s = sigma + C[d];
         S[d] = s;
         Pidx[d] = s + c - 1;
-        Plen[d] = cnt[d] & (b - 1);
+        Plen[d] = span(d) & (b - 1);
         if (est) est[d] = E[d];
     }
     if (tid == 0) *f = sigma + total;
@@ -214,6 +223,29 @@ __global__ void k_fixup(uint32_t* __restrict__ pi_old, uint32_t* __restrict__ pi
             else hi = mid;
         }
         blen[j] = (lo < sigma && Pidx[lo] == j) ? Plen[lo] : (1u << log2b);
+    }
+}
+
+// After a packed round (plan_round): pi' over all npi + sigma logical blocks, as
+// k_fixup builds it.  The buckets' first blocks are their head blocks (logical
+// 0 .. sigma - 1 of the round's input); the round drew the first f - 2 sigma
+// entries of its pool (the sigma extra blocks npi .., then pi[sigma ..]); the
+// entries it left fill logical blocks 0 .. sigma - 1 and f .. npi + sigma - 1.
+__global__ void k_pack_fixup(const uint32_t* __restrict__ pi_old, uint32_t* __restrict__ pi_new,
+                             const uint32_t* __restrict__ S, const uint32_t* __restrict__ f_out,
+                             uint32_t sigma, uint32_t npi)
+{
+    const uint32_t npx = npi + sigma, f = min(max(*f_out, 2 * sigma), npx);
+    const uint32_t drawn = f - 2 * sigma;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < npx;
+         j += gridDim.x * blockDim.x) {
+        if (j < sigma) {
+            if (S[j] < npx) pi_new[S[j]] = pi_old[j];
+            const uint32_t k = drawn + j;  // < npi, as f <= npi + sigma
+            pi_new[j] = k < sigma ? npi + k : pi_old[k];
+        } else if (j >= f) {
+            pi_new[j] = pi_old[j - sigma];
+        }
     }
 }
 

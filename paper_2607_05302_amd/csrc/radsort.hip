@@ -101,12 +101,14 @@ struct Geo {
     uint32_t supers = 0, oop_supers = 0;  // super-tiles of a Radsort / out-of-place round
     uint32_t oop_E = 0, oop_st_log2 = 0;  // tile and super-tile of the out-of-place round
     bool fin_temps = false;  // finalize scratch holds the two-kernel F1's temporary blocks
+    bool pack_ok = false;    // radsort_sort_pairs packs the last round (plan_round)
 };
 
 // Workspace regions (byte offsets), each 256-byte aligned.
 struct Layout {
     uint64_t Tk, Tv, pi0, pi1, blen, opened, S, Pidx, Plen, f, est, ctr, ring, agg, done,
         csum, stcnt, fin, alt_k, alt_v;
+    uint64_t Xk, Xv, pack;  // a packed last round only: sigma extra blocks, bucket table
     uint64_t consumed;  // ordering-check builds only: a tag per physical block
     uint64_t ring_bytes, fin_bytes, total;
 };
@@ -199,17 +201,29 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     // GPU is shared or that grid cannot cover the state; only the other form needs
     // temporary blocks in the workspace
     const bool shared = opts && (opts->flags & RADSORT_F_SHARED);
-    g.fin_temps = shared || !fin_coop(g.npi, g.b, g.kb + g.vb, device_cus()).covers;
+    const uint32_t cus = device_cus();
+    g.fin_temps = shared || !fin_coop(g.npi, g.b, g.kb + g.vb, cus).covers;
+    // the packed last round: its finalize is the cooperative F1 over n_pi + sigma
+    // blocks, then the spare blocks' slots copied into place (no compaction)
+    g.pack_ok = !shared && fin_coop(g.npi + g.sigma, g.b, g.kb + g.vb, cus).covers;
+#ifdef RS_DEBUG_ORDER
+    g.pack_ok = false;  // the ordering check follows the rounds of the paper
+#endif
     return RADSORT_OK;
 }
 
 // Finalize scratch (parallel Alg. 7): see kernels_finalize.hpp.
-uint64_t finalize_bytes(const Geo& g)
+uint64_t finalize_bytes(const Geo& g, bool pack)
 {
-    return fin_scratch_bytes(g.npi, g.n, g.b, g.kb + g.vb, g.fin_temps);
+    return fin_scratch_bytes(g.npi + (pack ? g.sigma : 0u), g.n, g.b, g.kb + g.vb,
+                             g.fin_temps && !pack);
 }
 
-Layout make_layout(const Geo& g, bool oop)
+// pack: the workspace of a sort whose last round is packed (Geo::pack_ok): sigma
+// extra blocks, and the block permutations and finalize arrays over n_pi + sigma
+// blocks.  The small arrays come first, so that the error word's place depends
+// on n_t and sigma only.
+Layout make_layout(const Geo& g, bool oop, bool pack = false)
 {
     Layout L{};
     uint64_t o = 0;
@@ -219,23 +233,30 @@ Layout make_layout(const Geo& g, bool oop)
         return at;
     };
     const uint64_t sig = g.sigma, nt = g.nt;
-    if (!oop) {
-        L.Tk = take(2 * sig * g.b * g.kb);
-        L.Tv = take(2 * sig * g.b * g.vb);
-        L.pi0 = take(4ull * g.npi);
-        L.pi1 = take(4ull * g.npi);
-        L.blen = take(4ull * g.npi);
-        L.opened = take(8ull * g.sigma);
-    } else {
-        L.alt_k = take(g.n * g.kb);
-        L.alt_v = take(g.n * g.vb);
-    }
+    pack = pack && !oop;
     L.S = take(4 * nt * sig);
     L.Pidx = take(4 * (nt + 1) * sig);
     L.Plen = take(4 * (nt + 1) * sig);
     L.f = take(4 * (nt + 1));
     L.est = take(4 * nt * sig);
     L.ctr = take(4 * (nt + 8));
+    if (!oop) {
+        const uint64_t npx = g.npi + (pack ? sig : 0);
+        L.Tk = take(2 * sig * g.b * g.kb);
+        L.Tv = take(2 * sig * g.b * g.vb);
+        L.pi0 = take(4ull * npx);
+        L.pi1 = take(4ull * npx);
+        L.blen = take(4ull * npx);
+        L.opened = take(8ull * g.sigma);
+        if (pack) {
+            L.Xk = take(sig * g.b * g.kb);
+            L.Xv = take(sig * g.b * g.vb);
+            L.pack = take(4 * (2 * sig + 2));
+        }
+    } else {
+        L.alt_k = take(g.n * g.kb);
+        L.alt_v = take(g.n * g.vb);
+    }
 #ifdef RS_DEBUG_ORDER
     L.consumed = oop ? 0 : take(4ull * g.npi);
 #endif
@@ -250,7 +271,7 @@ Layout make_layout(const Geo& g, bool oop)
     const uint64_t csum_bytes = align_up(4ull * ((supers + kScanRows) / kScanRows) * sig, 256);
     L.ring_bytes = agg_bytes + done_bytes + csum_bytes;
     const uint64_t st_bytes = align_up(4ull * (supers + 1) * sig, 256);
-    L.fin_bytes = oop ? 0 : finalize_bytes(g);
+    L.fin_bytes = oop ? 0 : finalize_bytes(g, pack);
     L.ring = take(std::max(L.ring_bytes + st_bytes, L.fin_bytes));
     L.agg = L.ring;
     L.done = L.ring + agg_bytes;
@@ -350,6 +371,7 @@ struct radsort_state {
     bool dynamic = false;      // launch forms that need no co-residency (shared GPU)
     bool shared = false;       // other work shares the GPU: no cooperative launch at all
     bool seq_draws = false;    // draws in the sequential pool order (RADSORT_F_SEQ_DRAWS)
+    bool pack = false;         // the last round is packed (workspace laid out for it)
     int msd_shift = -1;        // >= 0: the rounds sort the digit at this shift (MSD split)
     bool debug_order = false;  // ordering-check builds: RADSORT_F_DEBUG_ORDER
     bool debug_plant = false;  // ... and RADSORT_F_DEBUG_PLANT: marks with a wrong tag
@@ -427,12 +449,12 @@ void launch_super_counts(const Geo& g, const typename UInt<KB>::T* Ak,
                          const typename UInt<KB>::T* Tk, const uint32_t* pi,
                          const uint32_t* blen, const uint32_t* f_in, uint32_t shift,
                          uint32_t* stcnt, uint32_t* csum, uint32_t* err, uint32_t* done_ctr,
-                         uint32_t r, PlanPtrs p, hipStream_t s)
+                         uint32_t r, PlanPtrs p, hipStream_t s, bool packed = false)
 {
     const uint32_t rows = (OOP ? g.oop_supers : g.supers) + 1;
     const uint32_t sts_log2 = OOP ? g.oop_st_log2 + (uint32_t)ilog2(g.oop_E)
                                   : g.st_log2 + (uint32_t)ilog2(g.E);
-    const uint32_t sig = g.sigma, plan = OOP ? 2u : 1u;
+    const uint32_t sig = g.sigma, plan = OOP ? 2u : packed ? 3u : 1u;
     PlanPtrs pr{p.S + r * sig, p.Pidx + (r + 1) * sig, p.Plen + (r + 1) * sig, p.f + r + 1,
                 p.est + r * sig};
     // one chunk of rows: the counting kernel's last workgroup scans and plans
@@ -610,6 +632,16 @@ template <int KB, int VB> struct Ops {
         a.npi = g.npi;
         a.ring_log2 = g.ring_log2;
         a.st_log2 = g.st_log2;
+        // the last round of a packed sort (plan_round, k_round): its buckets start at
+        // their final offsets and it draws from sigma extra blocks first
+        const bool packed = st->pack && r + 1 == g.nt && st->msd_shift < 0;
+        a.npi_x = packed ? g.npi + g.sigma : g.npi;
+        if (packed) {
+            a.pack_est = st->u32(st->L.est) + r * g.sigma;
+            a.Xk = (K*)(st->ws + st->L.Xk);
+            a.Xv = (V*)(st->ws + st->L.Xv);
+            launch_fill(a.pi_new + g.npi, g.sigma, kEmpty, s);  // entries past n_pi unset
+        }
 #ifdef RS_TIMELINE
         a.tl = g.tiles <= g_tl_tiles ? g_tl : nullptr;
 #endif
@@ -624,18 +656,23 @@ template <int KB, int VB> struct Ops {
         g_timer.mark(kCountBegin, r, s);
         launch_super_counts<KB, false>(g, a.Ak, a.Tk, a.pi_old, a.blen, a.f_in, a.shift, stcnt,
                                        st->u32(st->L.csum), a.err, a.tile_ctr + 1, r,
-                                       st->plan(), s);
+                                       st->plan(), s, packed);
         g_timer.mark(kRoundBegin, r, s);
         int rc = launch_round_t<KB, VB, false>(g, a, s, st->dynamic, st->seq_draws);
         if (rc) return rc;
         g_timer.mark(kRoundEnd, r, s);
-        uint32_t grid = (uint32_t)std::min<uint64_t>((g.npi + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_fixup, dim3(grid), dim3(256), 0, s, st->pi(st->cur),
-                           st->pi(st->cur ^ 1), a.S, st->u32(st->L.f) + r + 1,
-                           st->u32(st->L.Pidx) + (r + 1) * g.sigma,
-                           st->u32(st->L.Plen) + (r + 1) * g.sigma, st->u32(st->L.blen),
-                           a.opened, g.sigma, g.log2b, g.npi, st->u32(st->L.ring),
-                           st->L.ring_bytes / 4);
+        uint32_t grid = (uint32_t)std::min<uint64_t>((a.npi_x + 255) / 256, 4096);
+        if (packed)
+            hipLaunchKernelGGL(k_pack_fixup, dim3(grid), dim3(256), 0, s, st->pi(st->cur),
+                               st->pi(st->cur ^ 1), a.S, st->u32(st->L.f) + r + 1, g.sigma,
+                               g.npi);
+        else
+            hipLaunchKernelGGL(k_fixup, dim3(grid), dim3(256), 0, s, st->pi(st->cur),
+                               st->pi(st->cur ^ 1), a.S, st->u32(st->L.f) + r + 1,
+                               st->u32(st->L.Pidx) + (r + 1) * g.sigma,
+                               st->u32(st->L.Plen) + (r + 1) * g.sigma, st->u32(st->L.blen),
+                               a.opened, g.sigma, g.log2b, g.npi, st->u32(st->L.ring),
+                               st->L.ring_bytes / 4);
         g_timer.mark(kFixupEnd, r, s);
         st->cur ^= 1;
         st->rounds_done++;
@@ -671,7 +708,16 @@ template <int KB, int VB> struct Ops {
         a.sigma = g.sigma;
         a.log2b = g.log2b;
         a.npi = g.npi;
-        a.job = fin_job(g.npi);
+        a.npi_eq = g.npi;
+        if (st->pack && r == g.nt && st->msd_shift < 0) {  // the last round was packed
+            a.npi = g.npi + g.sigma;
+            a.Xk = (K*)(st->ws + st->L.Xk);
+            a.Xv = (V*)(st->ws + st->L.Xv);
+            a.est = st->u32(st->L.est) + (r - 1) * g.sigma;
+            a.S = st->u32(st->L.S) + (r - 1) * g.sigma;
+            a.pack = st->u32(st->L.pack);
+        }
+        a.job = fin_job(a.npi);
         a.err = st->err();
         a.scratch = st->ws + st->L.fin;
         a.spare_pi = st->pi(st->cur ^ 1);
@@ -1051,9 +1097,26 @@ int run_one(void* keys, void* vals, uint64_t n, int kb, int vb, SegChoice c, uin
 
 extern "C" {
 
+namespace {
+
+// pack: the state's last round is packed (radsort_sort_pairs), its workspace laid
+// out for that (make_layout)
+int state_create(radsort_state** out, void* keys, void* payload, uint64_t n, int key_bytes,
+                 int payload_bytes, int digit_bits, const radsort_opts* opts, bool pack);
+
+}  // namespace
+
 int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_t n,
                          int key_bytes, int payload_bytes, int digit_bits,
                          const radsort_opts* opts)
+{
+    return state_create(out, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts, false);
+}
+
+namespace {
+
+int state_create(radsort_state** out, void* keys, void* payload, uint64_t n, int key_bytes,
+                 int payload_bytes, int digit_bits, const radsort_opts* opts, bool pack)
 {
     if (!out) return RADSORT_E_INVALID;
     *out = nullptr;
@@ -1065,7 +1128,8 @@ int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_
     radsort_state* st = new (std::nothrow) radsort_state();
     if (!st) return RADSORT_E_NOMEM;
     st->g = g;
-    st->L = make_layout(g, false);
+    st->pack = pack && g.pack_ok;
+    st->L = make_layout(g, false, st->pack);
     st->keys = keys;
     st->vals = payload;
     st->count = n;
@@ -1094,6 +1158,8 @@ int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_
     *out = st;
     return RADSORT_OK;
 }
+
+}  // namespace
 
 int radsort_state_setup(radsort_state* st, void* stream)
 {
@@ -1230,7 +1296,7 @@ uint64_t radsort_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes, i
 {
     Geo g;
     if (make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts)) return 0;
-    return make_layout(g, false).total;
+    return make_layout(g, false, g.pack_ok).total;
 }
 
 uint64_t radsort_oop_workspace_bytes(uint64_t n, int key_bytes, int payload_bytes,
@@ -1251,8 +1317,9 @@ int radsort_workspace_error(const void* workspace, uint64_t n, int key_bytes, in
     int rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, opts);
     if (rc) return rc;
     if (n <= 1) return RADSORT_OK;  // such a call runs nothing
+    // the error word lies among the small arrays at the front of every layout
     const Layout L = make_layout(g, out_of_place != 0);
-    if (opts->workspace_bytes < L.total) return RADSORT_E_NOMEM;
+    if (opts->workspace_bytes < L.ctr + 4ull * (g.nt + 1)) return RADSORT_E_NOMEM;
     hipStream_t s = (hipStream_t)stream;
     uint32_t e = 0;
     RS_HIP(hipMemcpyAsync(&e, (const uint8_t*)workspace + L.ctr + 4ull * g.nt, 4,
@@ -1272,7 +1339,7 @@ int radsort_sort_pairs(void* keys, void* payload, uint64_t n, int key_bytes, int
     if (rc) return rc;
     if (n <= 1) return RADSORT_OK;
     radsort_state* st = nullptr;
-    rc = radsort_state_create(&st, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts);
+    rc = state_create(&st, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts, true);
     if (rc) return rc;
     // The launch form without co-residency (one workgroup per tile) is also the
     // faster one alone for blocks of up to 1024 elements (no cooperative launch per

@@ -217,22 +217,22 @@ def test_copy_argument_errors():
 
 
 def test_shared_calls_need_their_own_workspace_size():
-    """With RADSORT_F_SHARED finalize's block permutation takes its two-kernel form,
-    whose temporary blocks the workspace must hold: the size for shared calls is at
-    least the other, and a workspace sized without the flag is refused by a shared
-    call before any launch."""
+    """The workspace depends on RADSORT_F_SHARED: a shared call's finalize takes the
+    two-kernel form of its block permutation, whose temporary blocks the workspace
+    must hold, and packs no last round; an unshared call packs the last round, which
+    takes sigma extra blocks.  Each call refuses a workspace one byte smaller than its
+    own size, before any launch."""
     lib = radsort.load()
-    n = 1 << 28  # large enough that the temporaries outgrow the ring they share memory with
-    plain = radsort.workspace_bytes(n, 4, 4, 8, 1024)
-    shared = radsort.workspace_bytes(n, 4, 4, 8, 1024, shared=True)
-    assert shared > plain > 0
-    assert radsort.workspace_bytes(1 << 24, 4, 4, 8, 1024, shared=True) >= \
-        radsort.workspace_bytes(1 << 24, 4, 4, 8, 1024)
-    o = radsort.Opts()
-    o.block_elems = 1024
-    o.workspace = 0x1000  # never dereferenced: the size check comes first
-    o.workspace_bytes = plain
-    o.flags = radsort.F_SHARED
     fake = ctypes.c_void_p(0x1000)
-    assert lib.radsort_sort_pairs(fake, fake, n, 4, 4, 8, ctypes.byref(o), None) == \
-        radsort.E_NOMEM
+    for n, b in ((1 << 28, 1024), (1 << 28, 2048), (1 << 24, 1024)):
+        plain = radsort.workspace_bytes(n, 4, 4, 8, b)
+        shared = radsort.workspace_bytes(n, 4, 4, 8, b, shared=True)
+        assert plain > 0 and shared > 0 and plain != shared
+        for flags, size in ((radsort.F_SHARED, shared), (0, plain)):
+            o = radsort.Opts()
+            o.block_elems = b
+            o.workspace = 0x1000  # never dereferenced: the size check comes first
+            o.workspace_bytes = size - 1
+            o.flags = flags
+            assert lib.radsort_sort_pairs(fake, fake, n, 4, 4, 8, ctypes.byref(o), None) == \
+                radsort.E_NOMEM

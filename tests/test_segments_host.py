@@ -24,7 +24,7 @@ def test_workspace_covers_only_the_large_arrays():
     # larger arrays run the Radsort steps on the lanes, each lane its own workspace
     n = WG_MAX + 1
     big = np.array([0, n, n + 5], dtype=np.uint64)
-    one = radsort.workspace_bytes(n, 4, 4, 8, 2048)
+    one = radsort.workspace_bytes(n, 4, 4, 8, 2048, shared=True)  # the lanes run shared
     assert radsort.segments_workspace_bytes(big, 4, 4, None) >= one
     four = np.cumsum([0] + [n] * 4).astype(np.uint64)
     assert radsort.segments_workspace_bytes(four, 4, 4, None) >= 4 * one
