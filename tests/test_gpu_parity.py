@@ -186,6 +186,13 @@ E2E = [
     ("uniform", 2000, 8, 4, 1, 64),           # 1-bit digits: 64 rounds, the most there are
     ("zipf", 30000, 4, 4, 2, 64),
     ("few", 40000, 4, 4, 6, 256),
+    # the packed last round: many buckets within one block of A, blocks larger than a
+    # tile, fewer elements than a block, ragged tails
+    ("uniform", 300, 4, 4, 8, 64),
+    ("uniform", 70000, 4, 4, 8, 16384),
+    ("uniform", 5000, 8, 4, 8, 4096),
+    ("zipf", 123457, 4, 0, 8, 128),
+    ("low20", 1000003, 8, 8, 8, 512),
 ]
 
 
