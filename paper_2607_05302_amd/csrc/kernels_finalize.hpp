@@ -1058,7 +1058,7 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
                       bool temps, hipStream_t s)
 {
     const FinCoop coop = fin_coop(a.npi, 1u << a.log2b, KB + VB, lds_grid);
-    if (!coop.covers && (!temps || a.pack)) return -2;
+    if (!coop.covers && !temps) return -2;
     const uint32_t npi = a.npi, b = 1u << a.log2b;
     FinArrays f = fin_arrays(a.scratch, npi, a.n, a.spare_pi, a.spare_blen);
     const uint32_t grid = std::min<uint32_t>((npi + 255) / 256, 8192);

@@ -100,8 +100,9 @@ struct Geo {
     uint32_t st_log2 = 0;                 // tiles per super-tile: 2^st_log2
     uint32_t supers = 0, oop_supers = 0;  // super-tiles of a Radsort / out-of-place round
     uint32_t oop_E = 0, oop_st_log2 = 0;  // tile and super-tile of the out-of-place round
-    bool fin_temps = false;  // finalize scratch holds the two-kernel F1's temporary blocks
-    bool pack_ok = false;    // radsort_sort_pairs packs the last round (plan_round)
+    bool fin_temps = false;       // finalize scratch holds the two-kernel F1's temporary blocks
+    bool fin_temps_pack = false;  // the same for a packed state (n_pi + sigma blocks)
+    bool pack_ok = false;         // one-call sorts pack the last round (plan_round)
 };
 
 // Workspace regions (byte offsets), each 256-byte aligned.
@@ -203,9 +204,10 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     const bool shared = opts && (opts->flags & RADSORT_F_SHARED);
     const uint32_t cus = device_cus();
     g.fin_temps = shared || !fin_coop(g.npi, g.b, g.kb + g.vb, cus).covers;
-    // the packed last round: its finalize is the cooperative F1 over n_pi + sigma
-    // blocks, then the spare blocks' slots copied into place (no compaction)
-    g.pack_ok = !shared && fin_coop(g.npi + g.sigma, g.b, g.kb + g.vb, cus).covers;
+    // the packed last round: its finalize is F1 over n_pi + sigma blocks, then the
+    // spare blocks' slots copied into place (no compaction)
+    g.fin_temps_pack = shared || !fin_coop(g.npi + g.sigma, g.b, g.kb + g.vb, cus).covers;
+    g.pack_ok = true;
 #ifdef RS_DEBUG_ORDER
     g.pack_ok = false;  // the ordering check follows the rounds of the paper
 #endif
@@ -216,7 +218,7 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
 uint64_t finalize_bytes(const Geo& g, bool pack)
 {
     return fin_scratch_bytes(g.npi + (pack ? g.sigma : 0u), g.n, g.b, g.kb + g.vb,
-                             g.fin_temps && !pack);
+                             pack ? g.fin_temps_pack : g.fin_temps);
 }
 
 // pack: the workspace of a sort whose last round is packed (Geo::pack_ok): sigma
@@ -737,7 +739,8 @@ template <int KB, int VB> struct Ops {
             RS_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
             cus = (uint32_t)n_cu;
         }
-        const int fr = finalize_parallel<KB, VB>(a, (uint32_t)cap, cus, g.fin_temps, s);
+        const bool temps = a.pack ? g.fin_temps_pack : g.fin_temps;
+        const int fr = finalize_parallel<KB, VB>(a, (uint32_t)cap, cus, temps, s);
         int rc = fr == -2 ? RADSORT_E_NOMEM : fr ? RADSORT_E_DEVICE : RADSORT_OK;
         g_timer.mark(kFinEnd, 0, s);
         return rc;
@@ -986,7 +989,7 @@ int make_seg_plan(SegPlan& P, const uint64_t* off, uint32_t nseg, int kb, int vb
         Geo g;
         int rc = make_geo(g, n, kb, vb, (int)c.bits, &o);
         if (rc) return rc;
-        P.lane_bytes[l] = std::max(P.lane_bytes[l], make_layout(g, false).total);
+        P.lane_bytes[l] = std::max(P.lane_bytes[l], make_layout(g, false, g.pack_ok).total);
         P.large.push_back(i);
         P.lane.push_back(l);
         P.choice.push_back(c);
@@ -1072,6 +1075,11 @@ __global__ void k_or_error(const uint32_t* src, uint32_t* dst)
     if (threadIdx.x == 0 && *src) atomicOr(dst, *src);
 }
 
+// pack: the state's last round is packed (one-call sorts), its workspace laid out
+// for that (make_layout)
+static int state_create(radsort_state** out, void* keys, void* payload, uint64_t n, int key_bytes,
+                 int payload_bytes, int digit_bits, const radsort_opts* opts, bool pack);
+
 // the Radsort steps of one array on stream s, in the dynamic launch form; its
 // device error bits are ORed into *errs
 int run_one(void* keys, void* vals, uint64_t n, int kb, int vb, SegChoice c, uint8_t* ws,
@@ -1083,7 +1091,7 @@ int run_one(void* keys, void* vals, uint64_t n, int kb, int vb, SegChoice c, uin
     o.workspace = ws;
     o.workspace_bytes = ws_bytes;
     radsort_state* st = nullptr;
-    int rc = radsort_state_create(&st, keys, vals, n, kb, vb, (int)c.bits, &o);
+    int rc = state_create(&st, keys, vals, n, kb, vb, (int)c.bits, &o, true);
     if (rc) return rc;
     st->dynamic = true;
     st->shared = true;  // the lanes run concurrently: no cooperative launch
@@ -1095,27 +1103,7 @@ int run_one(void* keys, void* vals, uint64_t n, int kb, int vb, SegChoice c, uin
     return rc;
 }
 
-extern "C" {
-
-namespace {
-
-// pack: the state's last round is packed (radsort_sort_pairs), its workspace laid
-// out for that (make_layout)
-int state_create(radsort_state** out, void* keys, void* payload, uint64_t n, int key_bytes,
-                 int payload_bytes, int digit_bits, const radsort_opts* opts, bool pack);
-
-}  // namespace
-
-int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_t n,
-                         int key_bytes, int payload_bytes, int digit_bits,
-                         const radsort_opts* opts)
-{
-    return state_create(out, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts, false);
-}
-
-namespace {
-
-int state_create(radsort_state** out, void* keys, void* payload, uint64_t n, int key_bytes,
+static int state_create(radsort_state** out, void* keys, void* payload, uint64_t n, int key_bytes,
                  int payload_bytes, int digit_bits, const radsort_opts* opts, bool pack)
 {
     if (!out) return RADSORT_E_INVALID;
@@ -1159,7 +1147,14 @@ int state_create(radsort_state** out, void* keys, void* payload, uint64_t n, int
     return RADSORT_OK;
 }
 
-}  // namespace
+extern "C" {
+
+int radsort_state_create(radsort_state** out, void* keys, void* payload, uint64_t n,
+                         int key_bytes, int payload_bytes, int digit_bits,
+                         const radsort_opts* opts)
+{
+    return state_create(out, keys, payload, n, key_bytes, payload_bytes, digit_bits, opts, false);
+}
 
 int radsort_state_setup(radsort_state* st, void* stream)
 {
@@ -1708,7 +1703,7 @@ int radsort_sort_pairs_noalloc(void* keys, void* payload, uint64_t n, int key_by
     rc = make_geo(g, n, key_bytes, payload_bytes, digit_bits, &o);
     if (rc) return rc;
     if (n <= 1) return RADSORT_OK;
-    const Layout L = make_layout(g, false);
+    const Layout L = make_layout(g, false, g.pack_ok);
     if (L.total > (uint64_t)RADSORT_NOALLOC_SCRATCH_BYTES) return RADSORT_E_NOMEM;
     void* ws = nullptr;
     rc = scratch_address(&ws);
@@ -1722,6 +1717,7 @@ int radsort_sort_pairs_noalloc(void* keys, void* payload, uint64_t n, int key_by
     st.vals = payload;
     st.count = n;
     st.seq_draws = flags & RADSORT_F_SEQ_DRAWS;
+    st.pack = g.pack_ok;
     // the launch forms that query no occupancy (the query's cache allocates)
     st.dynamic = true;
     st.shared = true;

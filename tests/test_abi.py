@@ -219,15 +219,17 @@ def test_copy_argument_errors():
 def test_shared_calls_need_their_own_workspace_size():
     """The workspace depends on RADSORT_F_SHARED: a shared call's finalize takes the
     two-kernel form of its block permutation, whose temporary blocks the workspace
-    must hold, and packs no last round; an unshared call packs the last round, which
-    takes sigma extra blocks.  Each call refuses a workspace one byte smaller than its
-    own size, before any launch."""
+    must hold (they share memory with the look-back ring, so small states need no
+    more).  Each call refuses a workspace one byte smaller than its own size, before
+    any launch."""
     lib = radsort.load()
     fake = ctypes.c_void_p(0x1000)
     for n, b in ((1 << 28, 1024), (1 << 28, 2048), (1 << 24, 1024)):
         plain = radsort.workspace_bytes(n, 4, 4, 8, b)
         shared = radsort.workspace_bytes(n, 4, 4, 8, b, shared=True)
-        assert plain > 0 and shared > 0 and plain != shared
+        assert shared >= plain > 0
+        if n == 1 << 28:
+            assert shared > plain
         for flags, size in ((radsort.F_SHARED, shared), (0, plain)):
             o = radsort.Opts()
             o.block_elems = b
