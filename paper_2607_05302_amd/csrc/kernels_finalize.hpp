@@ -179,26 +179,36 @@ __global__ void k_fin_init(const uint32_t* __restrict__ pi, const uint32_t* __re
     }
 }
 
-// One doubling step: the window of 2^k successors becomes 2^(k+1).  (V, O) is
-// the smallest node in the window and the distance to its first occurrence.
-__global__ void k_fin_jump(const uint32_t* __restrict__ Ji, const uint32_t* __restrict__ Vi,
-                           const uint32_t* __restrict__ Oi, uint32_t* __restrict__ Jo,
-                           uint32_t* __restrict__ Vo, uint32_t* __restrict__ Oo, uint32_t npi,
-                           uint32_t window)
+// Pointer jumping, two doubling steps per launch.  (V, O) of node p is the
+// smallest node within the window of its next 2^k successors (p included) and the
+// distance to its first occurrence; J(p) is the node 2^k steps on.  One launch
+// takes the window to 2^(k+2) from the four windows that start at p, J(p), J(J(p))
+// and J(J(J(p))), in that order, so that the first occurrence of the smallest node
+// wins.
+__global__ void k_fin_jump4(const uint32_t* __restrict__ Ji, const uint32_t* __restrict__ Vi,
+                            const uint32_t* __restrict__ Oi, uint32_t* __restrict__ Jo,
+                            uint32_t* __restrict__ Vo, uint32_t* __restrict__ Oo, uint32_t npi,
+                            uint32_t window)
 {
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < npi;
          p += gridDim.x * blockDim.x) {
-        uint32_t q = Ji[p];
-        if (q >= npi) q = p;  // never for a permutation
-        uint32_t v = Vi[p], o = Oi[p];
-        const uint32_t v2 = Vi[q];
-        if (v2 < v) {
-            v = v2;
-            o = Oi[q] + window;
+        uint32_t v = Vi[p], o = Oi[p], q = p;
+#pragma unroll
+        for (uint32_t k = 1; k < 4; k++) {
+            uint32_t qn = Ji[q];
+            if (qn >= npi) qn = q;  // never for a permutation
+            q = qn;
+            const uint32_t v2 = Vi[q];
+            if (v2 < v) {
+                v = v2;
+                o = Oi[q] + k * window;
+            }
         }
+        uint32_t qn = Ji[q];
+        if (qn >= npi) qn = q;
         Vo[p] = v;
         Oo[p] = o;
-        Jo[p] = Ji[q];
+        Jo[p] = qn;
     }
 }
 
@@ -1089,9 +1099,10 @@ int finalize_parallel(FinArgs<KB, VB>& a, uint32_t compact_grid, uint32_t lds_gr
         uint32_t *J[2] = {f.j0, f.j1}, *Vv[2] = {f.v0, f.v1}, *O[2] = {f.o0, f.o1};
         hipLaunchKernelGGL(k_fin_init, dim3(grid), dim3(256), 0, s, a.pi, a.f, a.sigma, npi,
                            f.nxt, J[0], Vv[0], O[0], homes);
+        // windows of 4^k successors: ceil(log4 n_pi) launches
         int cur = 0;
-        for (uint64_t w = 1; w < npi; w <<= 1) {
-            hipLaunchKernelGGL(k_fin_jump, dim3(grid), dim3(256), 0, s, J[cur], Vv[cur], O[cur],
+        for (uint64_t w = 1; w < npi; w <<= 2) {
+            hipLaunchKernelGGL(k_fin_jump4, dim3(grid), dim3(256), 0, s, J[cur], Vv[cur], O[cur],
                                J[cur ^ 1], Vv[cur ^ 1], O[cur ^ 1], npi, (uint32_t)w);
             cur ^= 1;
         }
