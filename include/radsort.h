@@ -139,7 +139,10 @@ typedef struct radsort_stats {
  * for t = n_t-1 .. 0 a sort phase (Alg. 5) and a fixup phase (Alg. 6), then
  * finalize (Alg. 7).  Each round first counts the digits of its own input (the
  * histogram loop of Alg. 1, per group of tiles) and takes its bucket starts and
- * the P and f it leaves from those counts by closed forms.
+ * the P and f it leaves from those counts by closed forms.  The last round is
+ * packed (see radsort_workspace_bytes): every element lands at the slot of its
+ * final position, so that finalize permutes whole blocks and merges at most two
+ * partial blocks per bucket, with no compaction; the result is the same.
  *   key_bytes      4 or 8 (uint32 / uint64 keys; signed or float keys are not
  *                  handled: the order is that of the unsigned bit patterns)
  *   payload_bytes  0 (payload must be NULL), 4 or 8
