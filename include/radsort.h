@@ -141,8 +141,8 @@ typedef struct radsort_stats {
  * histogram loop of Alg. 1, per group of tiles) and takes its bucket starts and
  * the P and f it leaves from those counts by closed forms.  The last round is
  * packed (see radsort_workspace_bytes): every element lands at the slot of its
- * final position, so that finalize permutes whole blocks and merges at most two
- * partial blocks per bucket, with no compaction; the result is the same.
+ * final position, so that finalize permutes whole blocks and merges at most one
+ * partial block per bucket, with no compaction; the result is the same.
  *   key_bytes      4 or 8 (uint32 / uint64 keys; signed or float keys are not
  *                  handled: the order is that of the unsigned bit patterns)
  *   payload_bytes  0 (payload must be NULL), 4 or 8

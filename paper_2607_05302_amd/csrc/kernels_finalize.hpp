@@ -31,7 +31,8 @@
 // A packed state (its last round packed: every element already sits at the slot
 // of its final position) needs no F2 and no F3: F1 moves each block to the home
 // k_pack_homes gives it, over n_pi + sigma blocks, and k_pack_merge copies the
-// slots of the at most 2 sigma blocks that do not fill a block of A into place.
+// slots of the at most sigma blocks (one per bucket) that do not fill a block of A
+// into place.
 #pragma once
 
 #include <hip/hip_cooperative_groups.h>
