@@ -155,8 +155,17 @@ __global__ __launch_bounds__(NT) void k_column_scan(uint32_t* cnt, const uint32_
 {
     const uint32_t c = blockIdx.x, r0 = c * kScanRows, r1 = min(rows, r0 + kScanRows);
     for (uint32_t d = threadIdx.x; d < sigma; d += NT) {
+        // the earlier chunks' sums, eight loads in flight
+        uint32_t part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        uint32_t i = 0;
+        for (; i + 8 <= c; i += 8) {
+#pragma unroll
+            for (uint32_t u = 0; u < 8; u++) part[u] += csum[(uint64_t)(i + u) * sigma + d];
+        }
+        for (; i < c; i++) part[0] += csum[(uint64_t)i * sigma + d];
         uint32_t run = 0;
-        for (uint32_t i = 0; i < c; i++) run += csum[(uint64_t)i * sigma + d];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; u++) run += part[u];
         uint32_t x[kScanRows];
 #pragma unroll
         for (int i = 0; i < kScanRows; i++)
