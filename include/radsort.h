@@ -51,7 +51,8 @@ extern "C" {
 #define RADSORT_E_NOMEM (-2)        /* allocation failed or workspace too small */
 #define RADSORT_E_DEVICE (-3)       /* a HIP call failed; see radsort_strerror */
 #define RADSORT_E_UNSUPPORTED (-4)  /* n >= 2^32 or digit_bits 12 .. 16 */
-#define RADSORT_E_TIMEOUT (-5)      /* a device-side bounded wait gave up */
+#define RADSORT_E_TIMEOUT (-5)      /* a device-side check failed: a bounded wait gave
+                                       up, or an index left its range */
 #define RADSORT_E_ORDER (-6)        /* RADSORT_F_DEBUG_ORDER: a block was drawn before the
                                        loads of its readers were marked returned */
 
@@ -291,7 +292,7 @@ int radsort_state_finalize(radsort_state* st, void* stream);
 int radsort_state_finalize_sequential(radsort_state* st, void* stream);
 /* Waits for the stream and copies the state to host memory: pi (n_pi uint32),
  * P (sigma logical indices and sigma lengths, uint32) and f.  Any of the output
- * pointers may be NULL.  Returns RADSORT_E_TIMEOUT if a device wait gave up. */
+ * pointers may be NULL.  Returns RADSORT_E_TIMEOUT if a device-side check failed. */
 int radsort_state_read(radsort_state* st, uint32_t* pi, uint32_t* P_idx, uint32_t* P_len,
                        uint32_t* f, void* stream);
 /* Enqueues a gather of the used elements of logical blocks sigma .. f-1 in

@@ -1480,7 +1480,7 @@ const char* radsort_strerror(int code)
     case RADSORT_E_NOMEM: return "out of memory or workspace too small";
     case RADSORT_E_DEVICE: return hipGetErrorString(g_last_hip);
     case RADSORT_E_UNSUPPORTED: return "unsupported size or digit width";
-    case RADSORT_E_TIMEOUT: return "a device-side wait gave up (protocol error)";
+    case RADSORT_E_TIMEOUT: return "a device-side check failed (a bounded wait gave up or an index left its range)";
     case RADSORT_E_ORDER: return "ordering check: a block was drawn before its loads were marked";
     default: return "unknown error";
     }
