@@ -193,6 +193,10 @@ E2E = [
     ("uniform", 5000, 8, 4, 8, 4096),
     ("zipf", 123457, 4, 0, 8, 128),
     ("low20", 1000003, 8, 8, 8, 512),
+    # wide records (12 and 16 bytes: smaller tiles) and 11-bit digits, packed, ragged
+    ("uniform", (1 << 20) + 777, 8, 8, 11, 1024),
+    ("zipf", 777777, 4, 8, 11, 2048),
+    ("uniform", 3000001, 8, 8, 8, 4096),
 ]
 
 
