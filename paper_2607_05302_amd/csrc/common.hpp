@@ -10,10 +10,6 @@ namespace rs {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // an unset pi' entry
 
-// status words of the look-back ring: count | flag << 32 | epoch << 34
-constexpr uint64_t kFlagAgg = 1ull;
-constexpr uint64_t kFlagInc = 2ull;
-
 // error bits written by kernels into the state's error word
 constexpr uint32_t kErrSpin = 1u;      // a bounded wait gave up
 constexpr uint32_t kErrBounds = 2u;    // an index left its range

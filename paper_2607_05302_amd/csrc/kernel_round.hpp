@@ -2,17 +2,15 @@
 // out-of-place round of Alg. 1 built from the same tile code.
 //
 // A tile is E consecutive element slots of the logical block sequence
-// sigma .. f-1 (slot s of logical block L holds element s if s < len(L)).  The
-// kernel is persistent and launched cooperatively, so all its workgroups are
-// resident at once; workgroup w takes tiles w, w + G, w + 2G, ... (G workgroups).
-// A tile waits only on lower tiles, and the lowest unfinished tile has all of its
-// predecessors finished, so the waits always end.  (A shared tile counter would
-// serialise the launch on one atomic: about 11 ns per tile on MI355X.)  Tiles
-// come in super-tiles of 2^st_log2; a pass before the kernel gives the digit
-// counts before every super-tile (kernels_prefix.hpp).
+// sigma .. f-1 (slot s of logical block L holds element s if s < len(L)).  How
+// workgroups take tiles is the launch form (below); in every form a tile waits
+// only on lower tiles, and the lowest unfinished tile is being worked on with all
+// of its predecessors finished, so the waits always end.  Tiles come in
+// super-tiles of 2^st_log2; a pass before the kernel gives the digit counts
+// before every super-tile (kernels_prefix.hpp).
 //
-//   1  read the tile's blocks through pi (keys and payload) into registers; this
-//      is issued while the workgroup still works on its previous tile;
+//   1  read the tile's blocks through pi (keys and payload) into registers (with
+//      PF, while the workgroup still works on its previous tile);
 //   2  stable rank inside the tile, per wave: for each group of 64 slots, every
 //      lane ORs its lane bit into a wave-private LDS word of its digit and reads
 //      the word back, which gives the lanes holding the same digit; lower lanes
@@ -29,10 +27,11 @@
 //      is drawn when rank q b - 1 is written (eager allocation, Alg. 5).  Blocks
 //      are drawn from the pool pi_old[0..] in input order, as the sequential
 //      algorithm draws them: the first blocks of the buckets are pool entries
-//      0..sigma-1, block draws number sigma, sigma+1, ... in slot order.  A tile
-//      finds its draws' pool indices from base[] (draws in earlier tiles are
-//      F = sum_d floor(base[d]/b)) plus an in-tile prefix count in slot order,
-//      and publishes pi_new[S[d] + q] for each draw.  A bucket's block that holds
+//      0..sigma-1, block draws number sigma, sigma+1, ....  A tile finds its
+//      draws' pool indices from base[] (draws in earlier tiles are
+//      F = sum_d floor(base[d]/b)) plus its rank among the tile's own draws: in
+//      (digit, block) order by default, in slot order (the sequential order)
+//      with SEQ; it publishes pi_new[S[d] + q] for each draw.  A bucket's block that holds
 //      the tile's first elements of that digit was drawn by an earlier tile: its
 //      pi_new entry is requested as soon as base[] is known and waited for only
 //      after the tile's own draws are out (waiting first would chain each tile
@@ -44,12 +43,13 @@
 // floor(E_k / b), with E_k the elements of tiles <= k, and these tiles cover at
 // least ceil(E_k / b) logical blocks, so every drawn pool index names a
 // head-start block or an input block of a tile <= k.  A tile publishes its counts
-// only after its loads returned; before writing into drawn blocks a tile waits
-// for the counts of their tiles (those of its own super-tile it has already
-// read in the look-back) or for their done word.
+// only after its loads returned; before publishing its draws (later tiles write
+// into a drawn block as soon as they see its entry) a tile waits for the counts
+// of their tiles (those of its own super-tile it has already read in the
+// look-back) or for their done word.
 //
-// The pool order, and with it pi, P and f after every round, is the same as in
-// the sequential algorithm.
+// P and f after every round are those of the sequential algorithm, and so is pi
+// with SEQ; the default order permutes the pool entries within each tile.
 #pragma once
 
 #include <type_traits>
