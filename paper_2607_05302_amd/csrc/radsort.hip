@@ -68,7 +68,8 @@ int ilog2(uint64_t x)
 //     out (SPLIT).  Measured at 2^28 uint32 + uint32, b = 2048: Radsort round
 //     1.59 ms against 2.07 ms for shape 0, with one workgroup per tile;
 //   shapes 2-4 (tiles of 4096 slots, two to three workgroups per CU) measured
-//     slower (2.05-2.21 ms), shapes 5-6 (16 waves of 8 slots) spill registers;
+//     slower (2.10-2.42 ms against 1.56 ms for shape 1, the same day), shapes
+//     5-6 (16 waves of 8 slots) spill registers;
 //     they are kept for measurement only (RS_ROUND_CFG selects a shape at build
 //     time, RS_RADSORT_FORM the launch form of the Radsort round).
 // The out-of-place round keeps shape 0 (1.50 ms, against 2.36 ms with shape 1).
