@@ -38,6 +38,28 @@ def test_noalloc_matches_sort_pairs_on_two_calls(kb, b, seq):
         assert torch.equal(v1, v2), n
 
 
+def test_noalloc_keys_only_then_wide_payload():
+    """Keys only (8-byte keys), then 4-byte keys with an 8-byte payload, on the
+    same scratch: the second call is smaller and its record size differs."""
+    n1, n2 = 3_000_017, 100_003
+    print(f"noalloc keys only kb=8 n={n1}", flush=True)
+    k1 = torch.from_numpy(workloads.uniform(0xA110E, n1, 8).view(np.int64)).to(DEV)
+    k2 = k1.clone()
+    radsort.sort_(k1, None, block_elems=1024, check=True)
+    radsort.sort_noalloc_(k2, None, block_elems=1024, check=True)
+    torch.cuda.synchronize()
+    assert torch.equal(k1, k2)
+    print(f"noalloc kb=4 vb=8 n={n2}", flush=True)
+    k1 = torch.from_numpy(workloads.uniform(0xA110F, n2, 4).view(np.int32)).to(DEV)
+    v1 = torch.arange(n2, dtype=torch.int64, device=DEV) * 3
+    k2, v2 = k1.clone(), v1.clone()
+    radsort.sort_(k1, v1, block_elems=512, check=True)
+    radsort.sort_noalloc_(k2, v2, block_elems=512, check=True)
+    torch.cuda.synchronize()
+    assert torch.equal(k1, k2)
+    assert torch.equal(v1, v2)
+
+
 def test_noalloc_refuses_a_workspace_past_the_scratch():
     lib = radsort.load()
     k, v = _pair(1024, 1, 4)
