@@ -28,9 +28,11 @@ import statistics
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-# the sources of the round kernel: counters taken on other text are stale
+# the sources of the round kernel and of the host code that picks its shape:
+# counters taken on other text are stale
 KERNEL_SOURCES = ["paper_2607_05302_amd/csrc/kernel_round.hpp",
-                  "paper_2607_05302_amd/csrc/common.hpp"]
+                  "paper_2607_05302_amd/csrc/common.hpp",
+                  "paper_2607_05302_amd/csrc/radsort.hip"]
 ROUND_KERNEL = "k_round<"
 COPY_KERNEL = "k_stream_copy"
 

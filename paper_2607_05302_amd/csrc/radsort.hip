@@ -93,6 +93,19 @@ template <int KB, int VB, bool WIDE, bool OOP = false> struct TileCfg {
     static constexpr int E = 64 * WAVES * ITEMS;
 };
 
+// The Radsort round's tile for large arrays of records of at most 8 bytes: shape 1
+// with 32 slots per lane (16384-slot tiles, one workgroup per compute unit).  Its
+// digit runs per tile are twice as long and the super-tiles half as many.
+// Measured with 8-bit digits and b = 2048 on uint32 + uint32: 8.20-8.27 ms per sort
+// at 2^28 against 8.47 ms with 8192-slot tiles; from 2^25 to 2^27 elements it is
+// no faster (fewer tiles in flight), so it is taken from kLargeTileMin on.
+struct LargeTile {
+    static constexpr int WAVES = 8, ITEMS = 32;
+    using Shape = RoundShape<WAVES, ITEMS, false, true, 2>;
+    static constexpr int E = 64 * WAVES * ITEMS;
+};
+constexpr uint64_t kLargeTileMin = 1ull << 28;  // elements
+
 struct Geo {
     uint64_t n = 0;
     uint32_t kb = 0, vb = 0, bits = 0, sigma = 0, nt = 0, b = 0, log2b = 0;
@@ -104,6 +117,7 @@ struct Geo {
     bool fin_temps = false;       // finalize scratch holds the two-kernel F1's temporary blocks
     bool fin_temps_pack = false;  // the same for a packed state (n_pi + sigma blocks)
     bool pack_ok = false;         // one-call sorts pack the last round (plan_round)
+    bool large_tile = false;      // the Radsort round runs LargeTile (E = 16384)
 };
 
 // Workspace regions (byte offsets), each 256-byte aligned.
@@ -173,7 +187,8 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     // pi entries are 32-bit with the top bit free; finalize scans at most 4096^2 entries
     if (npi >= (uint64_t)kScanTile * kScanTile) return RADSORT_E_UNSUPPORTED;
     g.npi = (uint32_t)npi;
-    g.E = tile_elems(g.kb, g.vb, g.bits, false);
+    g.large_tile = digit_bits <= 8 && key_bytes == 4 && payload_bytes <= 4 && n >= kLargeTileMin;
+    g.E = g.large_tile ? (uint32_t)LargeTile::E : tile_elems(g.kb, g.vb, g.bits, false);
     g.oop_E = tile_elems(g.kb, g.vb, g.bits, true);
 #ifdef RS_DEBUG_ORDER
     if (opts && (opts->flags & RADSORT_F_DEBUG_ORDER) && g.b > g.E) return RADSORT_E_UNSUPPORTED;
@@ -488,6 +503,9 @@ int launch_dynamic(const void* kern, uint32_t tiles, uint32_t threads, Args& a, 
     return RADSORT_OK;
 }
 
+#ifndef RS_RADSORT_FORM
+#define RS_RADSORT_FORM kPerTile
+#endif
 // seq: draws in the sequential pool order (pi as in the sequential algorithm);
 // otherwise in (digit, block) order within a tile.  Digits of more than 8 bits
 // always draw in the sequential order.  The out-of-place round draws nothing.
@@ -500,15 +518,24 @@ int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = 
     using NS = typename N::Shape;
     const uint32_t tiles = OOP ? (uint32_t)((g.n + g.oop_E - 1) / g.oop_E) : g.tiles;
     if (tiles == 0) return RADSORT_OK;
+    if constexpr (!OOP && KB == 4 && VB <= 4) {
+        if (g.large_tile) {  // 8-bit or narrower digits only (make_geo); a workgroup per tile
+            using LS = LargeTile::Shape;
+            constexpr int M = RS_RADSORT_FORM;
+            const void* kern =
+                seq ? (g.bits == 8 ? (const void*)&k_round<KB, VB, false, 8, 256, LS, M, true>
+                                   : (const void*)&k_round<KB, VB, false, 0, 256, LS, M, true>)
+                    : (g.bits == 8 ? (const void*)&k_round<KB, VB, false, 8, 256, LS, M, false>
+                                   : (const void*)&k_round<KB, VB, false, 0, 256, LS, M, false>);
+            return launch_dynamic(kern, tiles, 64 * LargeTile::WAVES, a, s, false);
+        }
+    }
     // shapes without register prefetch take a workgroup per tile (the persistent
     // form would hold the loop's state in registers the shape does not have)
     if (g.bits <= 8 && !N::PF) dyn = true;
     if (dyn) {
         // measured alone: one workgroup per tile for the Radsort round, the claim
         // loop for the out-of-place round
-#ifndef RS_RADSORT_FORM
-#define RS_RADSORT_FORM kPerTile
-#endif
         constexpr int M = OOP ? kClaimLoop : RS_RADSORT_FORM;
         const uint32_t nt = 64 * N::WAVES;
         const void* kern;
