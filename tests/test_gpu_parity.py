@@ -298,6 +298,19 @@ def test_large_uniform_u32_matches_oracle(b):
         assert np.array_equal(from_dev(dv, 4).astype(np.uint64), ov)
 
 
+def test_large_tile_keys_only_ragged():
+    """n = 2^28 + 12345 uint32 keys without payload, b = 4096: the 16384-slot tile of
+    large sorts with a ragged last tile and a partial last block, compared element by
+    element with the oracle."""
+    n = (1 << 28) + 12345
+    say(f"2^28+12345 uint32 keys only b=4096")
+    keys = workloads.uniform(0x5EED00A1, n, 4)
+    ok, _ = oracle.radsort(keys, None, 256, 4, 4096)
+    dk = to_dev(keys)
+    radsort.sort_(dk, None, block_elems=4096, check=True)
+    assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
+
+
 @pytest.mark.parametrize("dist", ["zipf", "equal", "sorted", "low20"])
 def test_structured_u64_2e30(dist):
     """n = 2^30 uint64 keys + uint32 index, 8-bit digits (8 rounds), b = 1024.  The
