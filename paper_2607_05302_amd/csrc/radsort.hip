@@ -94,13 +94,15 @@ template <int KB, int VB, bool WIDE, bool OOP = false> struct TileCfg {
 };
 
 // The Radsort round's tile for large arrays of records of at most 8 bytes: shape 1
-// with 32 slots per lane (16384-slot tiles, one workgroup per compute unit).  Its
-// digit runs per tile are twice as long and the super-tiles half as many.
-// Measured with 8-bit digits and b = 2048 on uint32 + uint32: 8.20-8.27 ms per sort
-// at 2^28 against 8.47 ms with 8192-slot tiles; from 2^25 to 2^27 elements it is
-// no faster (fewer tiles in flight), so it is taken from kLargeTileMin on.
-struct LargeTile {
-    static constexpr int WAVES = 8, ITEMS = 32;
+// with twice the slots per lane (4-byte keys: 16384-slot tiles; 8-byte keys without
+// payload: 8192), one workgroup per compute unit.  Its digit runs per tile are twice
+// as long and the super-tiles half as many.  Measured with 8-bit digits: uint32 +
+// uint32 at 2^28, b = 2048, 8.20-8.27 ms per sort against 8.47 ms with the smaller
+// tile (from 2^25 to 2^27 elements no faster: fewer tiles in flight, so it is taken
+// from kLargeTileMin on); uint64 keys at b = 4096, 18.8 against 19.6 ms at 2^28 and
+// 76.5 against 81.1 ms at 2^30.
+template <int KB> struct LargeTile {  // KB = 4: keys of 4 bytes; 8: keys of 8 bytes, no payload
+    static constexpr int WAVES = 8, ITEMS = KB == 4 ? 32 : 16;
     using Shape = RoundShape<WAVES, ITEMS, false, true, 2>;
     static constexpr int E = 64 * WAVES * ITEMS;
 };
@@ -187,8 +189,10 @@ int make_geo(Geo& g, uint64_t n, int key_bytes, int payload_bytes, int digit_bit
     // pi entries are 32-bit with the top bit free; finalize scans at most 4096^2 entries
     if (npi >= (uint64_t)kScanTile * kScanTile) return RADSORT_E_UNSUPPORTED;
     g.npi = (uint32_t)npi;
-    g.large_tile = digit_bits <= 8 && key_bytes == 4 && payload_bytes <= 4 && n >= kLargeTileMin;
-    g.E = g.large_tile ? (uint32_t)LargeTile::E : tile_elems(g.kb, g.vb, g.bits, false);
+    g.large_tile = digit_bits <= 8 && n >= kLargeTileMin &&
+                   ((key_bytes == 4 && payload_bytes <= 4) || (key_bytes == 8 && payload_bytes == 0));
+    g.E = !g.large_tile ? tile_elems(g.kb, g.vb, g.bits, false)
+          : key_bytes == 4 ? (uint32_t)LargeTile<4>::E : (uint32_t)LargeTile<8>::E;
     g.oop_E = tile_elems(g.kb, g.vb, g.bits, true);
 #ifdef RS_DEBUG_ORDER
     if (opts && (opts->flags & RADSORT_F_DEBUG_ORDER) && g.b > g.E) return RADSORT_E_UNSUPPORTED;
@@ -518,16 +522,16 @@ int launch_round_t(const Geo& g, TileArgs<KB, VB>& a, hipStream_t s, bool dyn = 
     using NS = typename N::Shape;
     const uint32_t tiles = OOP ? (uint32_t)((g.n + g.oop_E - 1) / g.oop_E) : g.tiles;
     if (tiles == 0) return RADSORT_OK;
-    if constexpr (!OOP && KB == 4 && VB <= 4) {
+    if constexpr (!OOP && ((KB == 4 && VB <= 4) || (KB == 8 && VB == 0))) {
         if (g.large_tile) {  // 8-bit or narrower digits only (make_geo); a workgroup per tile
-            using LS = LargeTile::Shape;
+            using LS = typename LargeTile<KB>::Shape;
             constexpr int M = RS_RADSORT_FORM;
             const void* kern =
                 seq ? (g.bits == 8 ? (const void*)&k_round<KB, VB, false, 8, 256, LS, M, true>
                                    : (const void*)&k_round<KB, VB, false, 0, 256, LS, M, true>)
                     : (g.bits == 8 ? (const void*)&k_round<KB, VB, false, 8, 256, LS, M, false>
                                    : (const void*)&k_round<KB, VB, false, 0, 256, LS, M, false>);
-            return launch_dynamic(kern, tiles, 64 * LargeTile::WAVES, a, s, false);
+            return launch_dynamic(kern, tiles, 64 * LargeTile<KB>::WAVES, a, s, false);
         }
     }
     // shapes without register prefetch take a workgroup per tile (the persistent

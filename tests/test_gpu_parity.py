@@ -311,6 +311,19 @@ def test_large_tile_keys_only_ragged():
     assert np.array_equal(from_dev(dk, 4).astype(np.uint64), ok)
 
 
+def test_large_tile_u64_keys_only_ragged():
+    """n = 2^28 + 777 uint64 keys without payload, b = 4096: the large tile of 8-byte
+    keys (8192 slots, one workgroup per compute unit) with a ragged last tile,
+    compared element by element with the oracle."""
+    n = (1 << 28) + 777
+    say(f"2^28+777 uint64 keys only b=4096")
+    keys = workloads.uniform(0x5EED00A2, n, 8)
+    ok, _ = oracle.radsort(keys, None, 256, 8, 4096)
+    dk = to_dev(keys)
+    radsort.sort_(dk, None, block_elems=4096, check=True)
+    assert np.array_equal(from_dev(dk, 8).astype(np.uint64), ok)
+
+
 @pytest.mark.parametrize("dist", ["zipf", "equal", "sorted", "low20"])
 def test_structured_u64_2e30(dist):
     """n = 2^30 uint64 keys + uint32 index, 8-bit digits (8 rounds), b = 1024.  The
